@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""KPM moment throughput on one MI355X.
+
+A timed "step" is one pass of the whole hot path over one input: operator preparation
+H~ = (H - b)/a from device-resident inputs, the start vectors, floor(M/2) fused recursion
+steps with their dot products, the moment reduction, and the Jackson-damped DoS.
+
+Default workload: 3D cubic 64^3 lattice, periodic, spin hopping from seeded classical spins
+uniform on the sphere, M = 1024 moments, R = 32 random-phase vectors, complex64 recursion
+with FP64 moment accumulation; the plain FP64 (complex128) path is timed beside it.
+
+Prints one JSON line.  `--gpus N` with N > 1 is refused: this build measures one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "site·moment·vector updates/s + % HBM peak; p50/p99 solve latency vs plain FP64"
+UNIT = "site·moment·vector updates/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes_per_step(N, R, cplx, esz, has_diag, bonds_per_site):
+    """Bytes one recursion step must move: read r_n, read r_{n-1}, write r_{n+1} (3 N R e),
+    plus the operator: d_i (if present) and the forward bonds of each site."""
+    e = esz * (2 if cplx else 1)
+    meta = N * ((esz if has_diag else 0) + bonds_per_site * 2 * esz)
+    return 3 * N * R * e + meta
+
+
+def cpu_baseline(lat, a, b, vec, seed):
+    """The oracle (plain FP64 CPU code) on a bounded sample of the same lattice."""
+    import oracle
+    oracle.build()
+    threads = oracle.max_threads()
+    Ms, Rs = 64, 4
+    t0 = time.perf_counter()
+    oracle.moments_lattice(lat.dim, lat.L[:lat.dim], lat.t, a, b, Ms, Rs, vec_kind=vec, seed=seed,
+                           hop=lat.hop, onsite=lat.onsite, spinor=lat.spinor)
+    dt = time.perf_counter() - t0
+    return {"value": lat.N * Ms * Rs / dt, "unit": UNIT, "cores": threads, "kind": "oracle",
+            "sample": f"full {lat.N}-site lattice, M={Ms} moments, R={Rs} vectors ({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--fp64-steps", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--tpt", type=int, default=0, help="chunks per thread per tile (1, 2, 4)")
+    ap.add_argument("--max-blocks", type=int, default=0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        log("bench.py: only --gpus 1 is supported (single-GPU build; sharding is described in DESIGN.md)")
+        sys.exit(2)
+
+    import torch
+    import paper_1105_5481_amd as kpm
+    from paper_1105_5481_amd import workloads as wl
+
+    if not torch.cuda.is_available():
+        log("bench.py: no GPU visible")
+        sys.exit(1)
+    kpm.lib()
+    if args.tpt or args.max_blocks:
+        kpm.set_launch(args.tpt, args.max_blocks)
+    dev = "cuda"
+    stream = torch.cuda.current_stream()
+
+    cfg = wl.config2()
+    lat, M, R, vec, seed = cfg["lattice"], cfg["M"], cfg["R"], cfg["vec"], cfg["seed"]
+    K_dos = 2 * M
+    N = lat.N
+    log(f"bench: workload {cfg['name']} N={N} M={M} R={R}")
+
+    # device-resident inputs and the descriptor pointing at them
+    desc, keep = kpm._desc_for(lat, dev)
+    lo, hi = kpm.gershgorin(lat)
+    a, b = kpm.scale_from_bounds(lo, hi, 0.01)
+
+    def make_solver(prec):
+        h = kpm.Hamiltonian(lat, a, b, prec)
+        nbytes = h.workspace_bytes(M, R, vec)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        mu = torch.empty(M, dtype=torch.float64, device=dev)
+        om = torch.empty(K_dos, dtype=torch.float64, device=dev)
+        rho = torch.empty(K_dos, dtype=torch.float64, device=dev)
+        return h, ws, nbytes, mu, om, rho
+
+    L = kpm.lib()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    K = M // 2
+
+    def run_step(state, instance, ev=None):
+        h, ws, nbytes, mu, om, rho = state
+        kpm._check(L.kpm_update(h.handle, ctypes.byref(desc), a, b, sp), "kpm_update")            # a0
+        s = ctypes.c_void_p()
+        kpm._check(L.kpm_solve_begin(h.handle, M, R, vec, seed, instance, ws.data_ptr(), nbytes, sp,
+                                     ctypes.byref(s)), "kpm_solve_begin")                         # a1
+        if ev is not None:
+            ev[0].record(stream)
+        rem = ctypes.c_int32()
+        kpm._check(L.kpm_solve_advance(s, K, sp, ctypes.byref(rem)), "kpm_solve_advance")           # a2-a3, a5
+        if ev is not None:
+            ev[1].record(stream)
+        kpm._check(L.kpm_solve_finish(s, mu.data_ptr(), sp), "kpm_solve_finish")                   # a4
+        L.kpm_solve_free(s)
+        kpm._check(L.kpm_dos(mu.data_ptr(), M, 1, K_dos, a, b, om.data_ptr(), rho.data_ptr(), sp), "kpm_dos")
+
+    def timed(state, steps, warmup, tag):
+        for w in range(warmup):
+            run_step(state, 1000 + w)
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s_ in range(steps):
+            run_step(state, s_, evs[s_])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rec_ms = sum(e0.elapsed_time(e1) for e0, e1 in evs) / steps       # K-1 recursion launches per step
+        log(f"bench: {tag}: {dt / steps * 1e3:.3f} ms/step, recursion {rec_ms:.3f} ms/step")
+        return dt, rec_ms
+
+    s32 = make_solver(kpm.F32)
+    dt32, rec32 = timed(s32, args.steps, args.warmup, "c64")
+    ms_per_step = dt32 / args.steps * 1e3
+    updates = float(N) * M * R
+    value = updates / (dt32 / args.steps)
+    nrec = K - 1
+    step_us = rec32 * 1e3 / nrec
+    bytes_step = algorithmic_bytes_per_step(N, R, True, 4, s32[0].b != 0.0 or lat.onsite is not None, 3)
+    achieved = bytes_step / (step_us * 1e-6) / 1e9
+    mu32 = s32[3].cpu().numpy()
+
+    out = {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64", "data": "synthetic",
+        "config": {"workload": "3D cubic 64^3 periodic lattice, spin hopping from seeded spins uniform on the "
+                               "sphere, M=1024 moments, R=32 random-phase vectors, complex64 recursion, FP64 "
+                               "moments, Jackson DoS on 2048 points",
+                   "N": N, "M": M, "R": R, "recursion": "complex64", "moments": "fp64"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_step<float, OP_SPIN3>", "bytes_per_launch": bytes_step,
+                     "avg_launch_us": step_us},
+    }
+
+    if not args.no_fp64:
+        s64 = make_solver(kpm.F64)
+        dt64, rec64 = timed(s64, args.fp64_steps, 1, "c128")
+        v64 = updates / (dt64 / args.fp64_steps)
+        mu64 = s64[3].cpu().numpy()
+        import numpy as np
+        out["fp64_path"] = {"value": v64, "unit": UNIT, "ms_per_step": dt64 / args.fp64_steps * 1e3,
+                            "dtype": "c128", "speedup_c64_over_c128": value / v64,
+                            "c64_max_abs_err_vs_c128": float(np.abs(mu32 - mu64).max())}
+        s64[0].free()
+
+    if not args.no_cpu_baseline:
+        log("bench: timing the oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(lat, a, b, vec, seed)
+
+    s32[0].free()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

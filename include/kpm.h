@@ -1,0 +1,206 @@
+/*
+ * kpm.h -- C ABI of libkpm, the MI355X (gfx950) implementation of the hot
+ * path of the Kernel Polynomial Method (KPM): the Chebyshev vector recursion
+ * over R random vectors on a rescaled sparse tight-binding Hamiltonian, fused
+ * with the moment dot products, plus the Jackson-damped density of states.
+ *
+ * The method follows Zhang, Yamagiwa, Okumura, Yunoki, "Performance
+ * Acceleration of Kernel Polynomial Method Applying Graphics Processing
+ * Units" (2011), Sec. II-A and Sec. III:
+ *   H~ = (H - b) / a                       Eq. (tilde), a = alpha_-, b = alpha_+
+ *   |r_0> = xi, |r_1> = H~|r_0>, |r_{n+1}> = 2 H~|r_n> - |r_{n-1}>   Eq. (rn)
+ *   mu_n = 1/(N R) sum_r <r_0|r_n>          Eq. (munr), evaluated through
+ *   mu_{2n} = 2<r_n|r_n>/(N R) - mu_0,  mu_{2n+1} = 2 Re<r_{n+1}|r_n>/(N R) - mu_1
+ *   f(x) = [g_0 mu_0 + 2 sum g_n mu_n T_n(x)] / (pi sqrt(1-x^2))     Eq. (fKPM)
+ *
+ * Conventions for every entry point:
+ *  - Pointers named *_dev are device pointers (HBM of the current HIP device);
+ *    all other pointers are host pointers.  The caller owns every array it
+ *    passes.  Device arrays must stay valid until the work enqueued on the
+ *    given stream has completed.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Work is enqueued asynchronously; outputs in device memory are valid once
+ *    the stream has reached that point.
+ *  - Every call returns a kpm_status and never aborts.  On an argument error
+ *    nothing is enqueued and outputs are left untouched.  KPM_ERR_DEVICE
+ *    reports a HIP runtime error seen while enqueuing.
+ *  - A kpm_ham or kpm_solve handle must not be used from two host threads at
+ *    the same time.  Two solves may run concurrently on different streams if
+ *    each has its own workspace.
+ */
+#ifndef KPM_H
+#define KPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    KPM_OK = 0,
+    KPM_ERR_INVALID_ARG = 1,   /* a size, pointer or enum is out of range          */
+    KPM_ERR_OUT_OF_MEMORY = 2, /* a device allocation failed                       */
+    KPM_ERR_DEVICE = 3,        /* a HIP call failed                                */
+    KPM_ERR_BOUNDS = 4,        /* scaled spectrum may leave [-1, 1], or divergence */
+    KPM_ERR_UNSUPPORTED = 5,   /* a size beyond what the kernels index             */
+    KPM_ERR_WORKSPACE = 6      /* workspace missing, misaligned or too small       */
+} kpm_status;
+
+/* Operator kinds.  Lattices are periodic; site i = x + Lx (y + Ly z). */
+typedef enum { KPM_SQUARE_2D = 2, KPM_CUBIC_3D = 3, KPM_CSR = 10 } kpm_kind;
+
+/* Lattice hopping.  REAL: H_ij = -t on every nearest-neighbour bond.
+ * SPIN: H_ij = -t u_i^dag u_j with u_i = (cos(theta_i/2), e^{i phi_i} sin(theta_i/2)),
+ * i.e. -t [cos(th_i/2) cos(th_j/2) + sin(th_i/2) sin(th_j/2) e^{-i(phi_i - phi_j)}]. */
+typedef enum { KPM_HOP_REAL = 0, KPM_HOP_SPIN = 1 } kpm_hop;
+
+/* Precision of the vector recursion.  Moments are always accumulated in FP64. */
+typedef enum { KPM_F64 = 0, KPM_F32 = 1 } kpm_prec;
+
+/* Start vectors (Sec. II-A, stochastic evaluation of traces), drawn on the
+ * device from Philox4x64-10 (Salmon et al., SC'11) with key (seed, 4) and
+ * counter (i, floor(r/4), instance, 0), word r mod 4:
+ *   RADEMACHER: xi_{r,i} = +1 or -1 (top bit of the word);   normalisation 1/(N R)
+ *   PHASE:      xi_{r,i} = e^{i phi}, phi = 2 pi (word >> 11) 2^-53; normalisation 1/(N R)
+ *   UNIT:       xi_r = e_j, j = (instance + r) mod N;        normalisation 1/R
+ * With UNIT and R = N the moments are the exact traces Tr T_n(H~)/N (Eq. (DoStr)). */
+typedef enum { KPM_VEC_RADEMACHER = 0, KPM_VEC_PHASE = 1, KPM_VEC_UNIT = 2 } kpm_vec;
+
+/* Hamiltonian description (Sec. II-A; the paper's lattice of Sec. IV-A is a
+ * KPM_CUBIC_3D with t = 1 and no on-site term).  All arrays are device arrays
+ * of FP64 values (indices as stated).
+ *   kind, L[0..2] (L[2] ignored for 2D), t, hop: lattice geometry and hopping;
+ *   onsite_dev: N on-site energies H_ii, or NULL for zero;
+ *   spinor_dev: N x 3 values (cos(th/2), sin(th/2) cos(phi), sin(th/2) sin(phi))
+ *               per site, required when hop == KPM_HOP_SPIN;
+ *   CSR (kind == KPM_CSR): n rows, row_ptr_dev[n+1] (int64), col_dev[nnz] (int32),
+ *               val_re_dev[nnz], val_im_dev[nnz] or NULL for a real matrix.
+ *               Entries with equal (row, col) are summed.  H must be Hermitian. */
+typedef struct {
+    int32_t kind;
+    int32_t hop;
+    int64_t L[3];
+    double t;
+    const double *onsite_dev;
+    const double *spinor_dev;
+    int64_t n;
+    int64_t nnz;
+    const int64_t *row_ptr_dev;
+    const int32_t *col_dev;
+    const double *val_re_dev;
+    const double *val_im_dev;
+} kpm_ham_desc;
+
+typedef struct kpm_ham kpm_ham;     /* opaque: the scaled operator in device memory */
+typedef struct kpm_solve kpm_solve; /* opaque: one solve whose state lives in a workspace */
+
+/* Human-readable name of a status code (static string). */
+const char *kpm_status_string(kpm_status st);
+
+/* Gershgorin bounds of H (Sec. II-A, below Eq. (tilde)):
+ *   E_lo = min_i (Re H_ii - sum_{j!=i} |H_ij|),  E_hi = max_i (Re H_ii + sum_{j!=i} |H_ij|),
+ * computed in FP64 on the device.  A lattice neighbour slot that wraps onto the
+ * site itself (extent 1 or 2) counts as an off-diagonal entry.
+ * bounds_dev: device array of 2 doubles receiving (E_lo, E_hi). */
+kpm_status kpm_bounds_gershgorin(const kpm_ham_desc *desc, double *bounds_dev, void *stream);
+
+/* Build the scaled operator H~ = (H - b)/a (Eq. (tilde)) in device memory that
+ * the handle owns (one hipMalloc, released by kpm_free), in the recursion
+ * precision `prec`.  The FP64 values are formed as d_i = (H_ii - b)/a and
+ * H~_ij = (H_ij)/a; the FP32 operator rounds these.  a > 0 is required; the
+ * caller is responsible for a and b enclosing the spectrum (see
+ * kpm_scale_from_bounds).  Enqueues one kernel on `stream`.
+ * Limits: N * (scalars per site) / 4 < 2^31; lattice extents < 2^31. */
+kpm_status kpm_build(const kpm_ham_desc *desc, double a, double b, int32_t prec,
+                     void *stream, kpm_ham **out);
+
+/* Re-prepare an existing operator from new inputs of the same shape (same kind,
+ * extents and hopping type; for CSR the same n, nnz and value type) and new
+ * a, b, reusing its device memory: nothing is allocated, one kernel is
+ * enqueued (CSR inputs are validated first, which synchronises the stream).
+ * For Monte-Carlo loops over perturbed spin textures and for serving. */
+kpm_status kpm_update(kpm_ham *h, const kpm_ham_desc *desc, double a, double b, void *stream);
+
+/* Release the operator's device memory (the caller synchronises first). */
+void kpm_free(kpm_ham *h);
+
+/* Number of sites N of the operator, or -1 for NULL. */
+int64_t kpm_ham_dim(const kpm_ham *h);
+
+/* alpha_-/alpha_+ of Eq. (tilde) from bounds, with a relative margin eps in [0, 1):
+ *   a = (E_hi - E_lo)/(2 - eps),  b = (E_hi + E_lo)/2.   (Host arithmetic only.) */
+kpm_status kpm_scale_from_bounds(double e_lo, double e_hi, double eps, double *a, double *b);
+
+/* Bytes of device workspace one solve with M moments and R vectors needs
+ * (the two vector blocks, per-tile reduction partials and the dot products);
+ * 0 on invalid arguments. */
+size_t kpm_workspace_bytes(const kpm_ham *h, int32_t M, int32_t R, int32_t vec);
+
+/* All M moments mu_0..mu_{M-1} (Eq. (munr) through the doubling identities)
+ * averaged over R start vectors of kind `vec`.  Runs floor(M/2) fused
+ * recursion steps.  workspace_dev: device memory of at least
+ * kpm_workspace_bytes(h, M, R, vec) bytes, 256-byte aligned, used as scratch
+ * for the whole call (no other call may use it until the stream reaches the
+ * end of this one).  mu_dev: device array of M doubles.  M >= 1, R >= 1. */
+kpm_status kpm_moments(kpm_ham *h, int32_t M, int32_t R, int32_t vec, uint64_t seed,
+                       uint64_t instance, void *workspace_dev, size_t ws_bytes,
+                       double *mu_dev, void *stream);
+
+/* The same solve split into chunks, so that a caller can interleave other work
+ * (serving) or stop and resume: begin draws r_0 and runs the first product;
+ * advance runs up to max_steps further recursion steps and reports how many
+ * remain; finish reduces the dot products and writes mu_dev[M].  The vector
+ * state stays resident in the workspace between calls.  The handle is host
+ * memory released by kpm_solve_free (which does not touch the workspace). */
+kpm_status kpm_solve_begin(kpm_ham *h, int32_t M, int32_t R, int32_t vec, uint64_t seed,
+                           uint64_t instance, void *workspace_dev, size_t ws_bytes,
+                           void *stream, kpm_solve **out);
+kpm_status kpm_solve_advance(kpm_solve *s, int32_t max_steps, void *stream, int32_t *remaining);
+kpm_status kpm_solve_finish(kpm_solve *s, double *mu_dev, void *stream);
+void kpm_solve_free(kpm_solve *s);
+
+/* Many independent solves in one set of launches (each recursion step of every
+ * instance runs in one grid; the reduction partials are per tile, so every
+ * instance's moments are bitwise equal to the same solve run alone).  All
+ * handles must share the recursion precision and, per launch group, the
+ * operator class; mixed classes are grouped internally.  Arrays of length
+ * `count`: h, M, R, seed, instance, mu_dev (device arrays of M[i] doubles). */
+size_t kpm_workspace_bytes_batched(kpm_ham *const *h, int32_t count, const int32_t *M,
+                                   const int32_t *R, int32_t vec);
+kpm_status kpm_moments_batched(kpm_ham *const *h, int32_t count, const int32_t *M,
+                               const int32_t *R, int32_t vec, const uint64_t *seed,
+                               const uint64_t *instance, void *workspace_dev, size_t ws_bytes,
+                               double *const *mu_dev, void *stream);
+
+/* Density of states, Eq. (fKPM), on the K first-kind Chebyshev points
+ * x_k = cos(pi (k + 1/2)/K), k = 0..K-1, in FP64 on the device:
+ *   rho(omega_k) = [g_0 mu_0 + 2 sum_{n=1}^{M-1} g_n mu_n cos(n theta_k)] / (pi a sin(theta_k)),
+ *   omega_k = a x_k + b, with the Jackson coefficients
+ *   g_n = [(M-n+1) cos(pi n/(M+1)) + sin(pi n/(M+1)) cot(pi/(M+1))]/(M+1)
+ * when jackson != 0, else g_n = 1.  mu_dev[M], omega_dev[K], rho_dev[K]. */
+kpm_status kpm_dos(const double *mu_dev, int32_t M, int32_t jackson, int32_t K, double a,
+                   double b, double *omega_dev, double *rho_dev, void *stream);
+
+/* The start vectors r_0 exactly as the recursion draws them, in FP64, layout
+ * [i][r] (real) or [i][r][2] (complex, re/im) with i < N, r < R.  complex_layout
+ * selects the second layout (PHASE always produces complex values).  For tests. */
+kpm_status kpm_start_vectors(int32_t vec, int32_t complex_layout, uint64_t seed,
+                             uint64_t instance, int64_t N, int32_t R, double *out_dev,
+                             void *stream);
+
+/* Launch-shape tuning (host state, process-wide): elements per thread per tile
+ * (1, 2 or 4) and the maximum blocks per launch for one instance (multiple of
+ * 8).  Values of 0 keep the current setting.  Results do not depend on them
+ * except through the reduction order of the per-tile partials; they are fixed
+ * per tile, so any setting gives bitwise-identical moments for a given
+ * elements-per-thread value. */
+kpm_status kpm_set_launch(int32_t elems_per_thread, int32_t max_blocks);
+kpm_status kpm_get_launch(int32_t *elems_per_thread, int32_t *max_blocks);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KPM_H */

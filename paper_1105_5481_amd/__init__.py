@@ -1,0 +1,330 @@
+"""paper_1105_5481_amd -- Kernel Polynomial Method hot path on MI355X (gfx950).
+
+A thin ctypes binding over libkpm.so (C ABI in include/kpm.h).  Every step of
+the computation runs in the library's HIP kernels; this module only marshals
+arguments.  PyTorch supplies device memory (tensors) and streams.  If the
+library is missing, every call raises KPMError: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+__all__ = [
+    "KPMError", "lib", "library_path", "Hamiltonian", "gershgorin", "scale_from_bounds", "moments",
+    "moments_batched", "dos", "start_vectors", "Solve", "set_launch", "get_launch", "workspace_bytes",
+    "F64", "F32", "VEC_RADEMACHER", "VEC_PHASE", "VEC_UNIT",
+]
+
+F64, F32 = 0, 1
+VEC_RADEMACHER, VEC_PHASE, VEC_UNIT = 0, 1, 2
+KIND_SQUARE_2D, KIND_CUBIC_3D, KIND_CSR = 2, 3, 10
+HOP_REAL, HOP_SPIN = 0, 1
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libkpm.so")
+_lib = None
+
+
+class KPMError(RuntimeError):
+    pass
+
+
+class HamDesc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("hop", ctypes.c_int32), ("L", ctypes.c_int64 * 3),
+                ("t", ctypes.c_double), ("onsite_dev", ctypes.c_void_p), ("spinor_dev", ctypes.c_void_p),
+                ("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("row_ptr_dev", ctypes.c_void_p),
+                ("col_dev", ctypes.c_void_p), ("val_re_dev", ctypes.c_void_p), ("val_im_dev", ctypes.c_void_p)]
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """Load libkpm.so (built in-tree by paper_1105_5481_amd/build.py)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise KPMError(f"libkpm.so not found at {_LIB_PATH}; build it with python paper_1105_5481_amd/build.py")
+    L = ctypes.CDLL(_LIB_PATH)
+    P, i32, i64, u64, f64, sz = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
+                                 ctypes.c_double, ctypes.c_size_t)
+    pdesc = ctypes.POINTER(HamDesc)
+    sigs = {
+        "kpm_status_string": (ctypes.c_char_p, [i32]),
+        "kpm_scale_from_bounds": (i32, [f64, f64, f64, P, P]),
+        "kpm_bounds_gershgorin": (i32, [pdesc, P, P]),
+        "kpm_build": (i32, [pdesc, f64, f64, i32, P, P]),
+        "kpm_free": (None, [P]),
+        "kpm_update": (i32, [P, pdesc, f64, f64, P]),
+        "kpm_ham_dim": (i64, [P]),
+        "kpm_workspace_bytes": (sz, [P, i32, i32, i32]),
+        "kpm_moments": (i32, [P, i32, i32, i32, u64, u64, P, sz, P, P]),
+        "kpm_solve_begin": (i32, [P, i32, i32, i32, u64, u64, P, sz, P, P]),
+        "kpm_solve_advance": (i32, [P, i32, P, P]),
+        "kpm_solve_finish": (i32, [P, P, P]),
+        "kpm_solve_free": (None, [P]),
+        "kpm_workspace_bytes_batched": (sz, [P, i32, P, P, i32]),
+        "kpm_moments_batched": (i32, [P, i32, P, P, i32, P, P, P, sz, P, P]),
+        "kpm_dos": (i32, [P, i32, i32, i32, f64, f64, P, P, P]),
+        "kpm_start_vectors": (i32, [i32, i32, u64, u64, i64, i32, P, P]),
+        "kpm_set_launch": (i32, [i32, i32]),
+        "kpm_get_launch": (i32, [P, P]),
+        "kpm_selftest_fastdiv": (i32, [ctypes.c_uint32, P, i32]),
+    }
+    for name, (res, args) in sigs.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(st: int, what: str):
+    if st != 0:
+        msg = lib().kpm_status_string(st).decode()
+        raise KPMError(f"{what}: {msg} (status {st})")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _dev(x, dtype, device):
+    torch = _torch()
+    if x is None:
+        return None
+    if isinstance(x, torch.Tensor):
+        return x.to(device=device, dtype=dtype).contiguous()
+    import numpy as np
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device=device, dtype=dtype)
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _desc_for(op, device):
+    """A kpm_ham_desc for a workloads.Lattice or workloads.CSR, plus the device tensors it points to."""
+    torch = _torch()
+    d = HamDesc()
+    keep = []
+    if hasattr(op, "row_ptr"):
+        rp = _dev(op.row_ptr, torch.int64, device)
+        cl = _dev(op.col, torch.int32, device)
+        vr = _dev(op.val_re, torch.float64, device)
+        vi = _dev(op.val_im, torch.float64, device) if op.val_im is not None else None
+        keep += [rp, cl, vr, vi]
+        d.kind = KIND_CSR
+        d.n = int(op.n)
+        d.nnz = int(op.row_ptr[-1])
+        d.row_ptr_dev, d.col_dev, d.val_re_dev, d.val_im_dev = _ptr(rp), _ptr(cl), _ptr(vr), _ptr(vi)
+    else:
+        d.kind = KIND_CUBIC_3D if op.dim == 3 else KIND_SQUARE_2D
+        d.hop = int(op.hop)
+        d.L[0], d.L[1], d.L[2] = int(op.L[0]), int(op.L[1]), int(op.L[2]) if op.dim == 3 else 1
+        d.t = float(op.t)
+        on = _dev(op.onsite, torch.float64, device) if op.onsite is not None else None
+        sp = _dev(op.spinor, torch.float64, device) if op.spinor is not None else None
+        keep += [on, sp]
+        d.onsite_dev, d.spinor_dev = _ptr(on), _ptr(sp)
+    return d, keep
+
+
+def scale_from_bounds(e_lo: float, e_hi: float, eps: float = 0.01):
+    a, b = ctypes.c_double(), ctypes.c_double()
+    _check(lib().kpm_scale_from_bounds(e_lo, e_hi, eps, ctypes.byref(a), ctypes.byref(b)), "kpm_scale_from_bounds")
+    return a.value, b.value
+
+
+def gershgorin(op, device="cuda", stream=None):
+    """(E_lo, E_hi) of a Lattice or CSR, computed on the device in FP64."""
+    torch = _torch()
+    d, keep = _desc_for(op, device)
+    out = torch.empty(2, dtype=torch.float64, device=device)
+    _check(lib().kpm_bounds_gershgorin(ctypes.byref(d), _ptr(out), _stream(stream)), "kpm_bounds_gershgorin")
+    torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+    lo, hi = out.tolist()
+    return lo, hi
+
+
+class Hamiltonian:
+    """The scaled operator H~ = (H - b)/a of Eq. (tilde), resident in device memory."""
+
+    def __init__(self, op, a: float, b: float, prec: int = F64, device="cuda", stream=None):
+        self.op, self.a, self.b, self.prec, self.device = op, float(a), float(b), int(prec), device
+        d, keep = _desc_for(op, device)
+        h = ctypes.c_void_p()
+        _check(lib().kpm_build(ctypes.byref(d), self.a, self.b, self.prec, _stream(stream), ctypes.byref(h)),
+               "kpm_build")
+        self._h = h
+        # the descriptor's arrays must live until the build kernel has run
+        (stream or _torch().cuda.current_stream()).synchronize()
+        del keep
+
+    def update(self, op, a: float, b: float, stream=None, keep_inputs: bool = False):
+        """Re-prepare H~ from new inputs of the same shape in place (no allocation).  The input
+        tensors are returned when keep_inputs is set (they must outlive the enqueued kernel);
+        otherwise the stream is synchronised before returning."""
+        d, keep = _desc_for(op, self.device)
+        _check(lib().kpm_update(self.handle, ctypes.byref(d), float(a), float(b), _stream(stream)), "kpm_update")
+        self.op, self.a, self.b = op, float(a), float(b)
+        if keep_inputs:
+            return keep
+        (stream or _torch().cuda.current_stream()).synchronize()
+        return None
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise KPMError("Hamiltonian already freed")
+        return self._h
+
+    @property
+    def N(self) -> int:
+        return int(lib().kpm_ham_dim(self.handle))
+
+    def workspace_bytes(self, M: int, R: int, vec: int) -> int:
+        n = lib().kpm_workspace_bytes(self.handle, M, R, vec)
+        if n == 0:
+            raise KPMError(f"invalid solve shape M={M} R={R} vec={vec}")
+        return int(n)
+
+    def free(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().kpm_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def workspace_bytes(ham: Hamiltonian, M: int, R: int, vec: int) -> int:
+    return ham.workspace_bytes(M, R, vec)
+
+
+def _workspace(nbytes: int, device, workspace=None):
+    torch = _torch()
+    if workspace is not None:
+        if workspace.numel() * workspace.element_size() < nbytes:
+            raise KPMError("workspace too small")
+        return workspace
+    # torch's caching allocator returns 512-byte aligned blocks
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def moments(ham: Hamiltonian, M: int, R: int, vec: int = VEC_RADEMACHER, seed: int = 0, instance: int = 0,
+            stream=None, out=None, workspace=None):
+    """mu_0..mu_{M-1} (device FP64 tensor) averaged over R start vectors."""
+    torch = _torch()
+    nb = ham.workspace_bytes(M, R, vec)
+    ws = _workspace(nb, ham.device, workspace)
+    mu = out if out is not None else torch.empty(M, dtype=torch.float64, device=ham.device)
+    _check(lib().kpm_moments(ham.handle, M, R, vec, seed, instance, ws.data_ptr(), nb, mu.data_ptr(),
+                             _stream(stream)), "kpm_moments")
+    return mu
+
+
+def moments_batched(hams: Sequence[Hamiltonian], M, R, vec: int = VEC_RADEMACHER, seeds=None, instances=None,
+                    stream=None, outs=None, workspace=None) -> List:
+    torch = _torch()
+    n = len(hams)
+    Ms = [int(M)] * n if isinstance(M, int) else [int(x) for x in M]
+    Rs = [int(R)] * n if isinstance(R, int) else [int(x) for x in R]
+    seeds = [0] * n if seeds is None else list(seeds)
+    instances = list(range(n)) if instances is None else list(instances)
+    harr = (ctypes.c_void_p * n)(*[h.handle.value for h in hams])
+    marr = (ctypes.c_int32 * n)(*Ms)
+    rarr = (ctypes.c_int32 * n)(*Rs)
+    sarr = (ctypes.c_uint64 * n)(*seeds)
+    iarr = (ctypes.c_uint64 * n)(*instances)
+    nb = lib().kpm_workspace_bytes_batched(harr, n, marr, rarr, vec)
+    if nb == 0:
+        raise KPMError("invalid batch")
+    ws = _workspace(nb, hams[0].device, workspace)
+    mus = outs if outs is not None else [torch.empty(m, dtype=torch.float64, device=hams[0].device) for m in Ms]
+    parr = (ctypes.c_void_p * n)(*[m.data_ptr() for m in mus])
+    _check(lib().kpm_moments_batched(harr, n, marr, rarr, vec, sarr, iarr, ws.data_ptr(), nb, parr,
+                                     _stream(stream)), "kpm_moments_batched")
+    return mus
+
+
+class Solve:
+    """A chunked solve: begin -> advance(k) ... -> finish; the vector state stays in `workspace`."""
+
+    def __init__(self, ham: Hamiltonian, M: int, R: int, vec: int = VEC_RADEMACHER, seed: int = 0,
+                 instance: int = 0, stream=None, workspace=None):
+        self.ham, self.M = ham, M
+        self.nbytes = ham.workspace_bytes(M, R, vec)
+        self.ws = _workspace(self.nbytes, ham.device, workspace)
+        s = ctypes.c_void_p()
+        _check(lib().kpm_solve_begin(ham.handle, M, R, vec, seed, instance, self.ws.data_ptr(), self.nbytes,
+                                     _stream(stream), ctypes.byref(s)), "kpm_solve_begin")
+        self._s = s
+
+    def advance(self, steps: int, stream=None) -> int:
+        rem = ctypes.c_int32()
+        _check(lib().kpm_solve_advance(self._s, steps, _stream(stream), ctypes.byref(rem)), "kpm_solve_advance")
+        return rem.value
+
+    def finish(self, out=None, stream=None):
+        torch = _torch()
+        mu = out if out is not None else torch.empty(self.M, dtype=torch.float64, device=self.ham.device)
+        _check(lib().kpm_solve_finish(self._s, mu.data_ptr(), _stream(stream)), "kpm_solve_finish")
+        return mu
+
+    def close(self):
+        if getattr(self, "_s", None) is not None and self._s.value:
+            lib().kpm_solve_free(self._s)
+        self._s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def dos(mu, K: int, a: float, b: float, jackson: bool = True, stream=None):
+    """(omega, rho) device tensors of Eq. (fKPM) on K Chebyshev points."""
+    torch = _torch()
+    M = mu.numel()
+    om = torch.empty(K, dtype=torch.float64, device=mu.device)
+    rho = torch.empty(K, dtype=torch.float64, device=mu.device)
+    _check(lib().kpm_dos(mu.data_ptr(), M, 1 if jackson else 0, K, float(a), float(b), om.data_ptr(),
+                         rho.data_ptr(), _stream(stream)), "kpm_dos")
+    return om, rho
+
+
+def start_vectors(vec: int, complex_layout: bool, seed: int, instance: int, N: int, R: int, device="cuda",
+                  stream=None):
+    torch = _torch()
+    cplx = complex_layout or vec == VEC_PHASE
+    out = torch.empty((N, R, 2) if cplx else (N, R), dtype=torch.float64, device=device)
+    _check(lib().kpm_start_vectors(vec, 1 if cplx else 0, seed, instance, N, R, out.data_ptr(), _stream(stream)),
+           "kpm_start_vectors")
+    return out
+
+
+def set_launch(elems_per_thread: int = 0, max_blocks: int = 0):
+    _check(lib().kpm_set_launch(elems_per_thread, max_blocks), "kpm_set_launch")
+
+
+def get_launch():
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().kpm_get_launch(ctypes.byref(a), ctypes.byref(b)), "kpm_get_launch")
+    return a.value, b.value

@@ -1,0 +1,935 @@
+// libkpm: C ABI (include/kpm.h) over the gfx950 kernels in kpm_kernels.hpp.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "kpm.h"
+#include "kpm_kernels.hpp"
+
+using namespace kpm;
+
+namespace {
+
+constexpr int PSLOTS_MAX = 64;          // ring slots of per-tile partials between reductions
+int g_tpt = 4;                          // chunks per thread per tile
+int g_max_blocks = 2048;                // blocks per instance per launch (multiple of 8)
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+inline hipStream_t S(void *s) { return (hipStream_t)s; }
+
+kpm_status check_launch()
+{
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? KPM_OK : KPM_ERR_DEVICE;
+}
+
+// ---------------------------------------------------------------------------
+// small utility kernels
+// ---------------------------------------------------------------------------
+constexpr int UPLOAD_WORDS = 896;
+struct UploadChunk {
+    uint32_t n;
+    uint32_t w[UPLOAD_WORDS];
+};
+__global__ void k_upload(uint32_t *dst, UploadChunk ch)
+{
+    for (uint32_t i = threadIdx.x; i < ch.n; i += blockDim.x) dst[i] = ch.w[i];
+}
+
+// Copy host bytes (multiple of 4) to device memory through kernel arguments,
+// so the host buffer may be released as soon as this returns.
+kpm_status upload(void *dst, const void *src, size_t bytes, hipStream_t st)
+{
+    const uint32_t *s = (const uint32_t *)src;
+    uint32_t *d = (uint32_t *)dst;
+    size_t words = bytes / 4;
+    UploadChunk ch;
+    for (size_t o = 0; o < words; o += UPLOAD_WORDS) {
+        ch.n = (uint32_t)std::min((size_t)UPLOAD_WORDS, words - o);
+        std::memcpy(ch.w, s + o, ch.n * 4);
+        hipLaunchKernelGGL(k_upload, dim3(1), dim3(256), 0, st, d + o, ch);
+    }
+    return check_launch();
+}
+
+// ---------------------------------------------------------------------------
+// operator preparation: H~ = (H - b)/a in the recursion precision
+// ---------------------------------------------------------------------------
+template <typename S>
+__global__ __launch_bounds__(256) void k_prep_lattice(uint32_t Lx, uint32_t Ly, uint32_t Lz, int dim, int spin,
+                                                      double t, double a, double b, const double *onsite,
+                                                      const double *spinor, int has_diag, S *diag, S *bond, S *hop)
+{
+    const uint32_t N = Lx * Ly * Lz;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) hop[0] = (S)((-t) / a);
+    if (i >= N) return;
+    if (has_diag) {
+        const double eps = onsite ? onsite[i] : 0.0;
+        diag[i] = (S)((eps - b) / a);
+    }
+    if (spin) {
+        const uint32_t x = i % Lx, y = (i / Lx) % Ly, z = i / (Lx * Ly);
+        const double ci = spinor[3 * (size_t)i], xi = spinor[3 * (size_t)i + 1], yi = spinor[3 * (size_t)i + 2];
+        for (int ax = 0; ax < dim; ++ax) {
+            uint32_t c[3] = {x, y, z};
+            const uint32_t L[3] = {Lx, Ly, Lz};
+            c[ax] = (c[ax] + 1) % L[ax];
+            const uint32_t j = c[0] + Lx * (c[1] + Ly * c[2]);
+            const double cj = spinor[3 * (size_t)j], xj = spinor[3 * (size_t)j + 1], yj = spinor[3 * (size_t)j + 2];
+            // z = u_i^dag u_j
+            const double zr = ci * cj + (xi * xj + yi * yj);
+            const double zi = xi * yj - yi * xj;
+            bond[((size_t)i * dim + ax) * 2] = (S)(((-t) * zr) / a);
+            bond[((size_t)i * dim + ax) * 2 + 1] = (S)(((-t) * zi) / a);
+        }
+    }
+}
+
+// CSR structure checks: row_ptr must start at 0, end at nnz and not decrease;
+// every column index must lie in [0, n).  Violations set *flag.
+__global__ void k_zero_int(int *flag)
+{
+    if (threadIdx.x == 0) *flag = 0;
+}
+__global__ __launch_bounds__(256) void k_check_rowptr(int64_t n, int64_t nnz, const int64_t *row_ptr, int *flag)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    const int64_t r = row_ptr[i];
+    bool bad = (i == 0 && r != 0) || (i == n && r != nnz) || (i < n && r > row_ptr[i + 1]);
+    if (bad) atomicOr(flag, 1);
+}
+__global__ __launch_bounds__(256) void k_check_cols(int64_t nnz, int64_t n, const int32_t *col, int *flag)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nnz && (col[k] < 0 || (int64_t)col[k] >= n)) atomicOr(flag, 2);
+}
+
+template <typename S>
+__global__ __launch_bounds__(256) void k_prep_csr(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                                                  const double *vre, const double *vim, double a, double b,
+                                                  S *diag, S *val, int cplx)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double hii = 0.0;
+    for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+        if (col[k] == i) {
+            hii = hii + vre[k];
+            if (cplx) {
+                val[2 * k] = (S)0;
+                val[2 * k + 1] = (S)0;
+            } else {
+                val[k] = (S)0;
+            }
+        } else if (cplx) {
+            val[2 * k] = (S)(vre[k] / a);
+            val[2 * k + 1] = (S)((vim ? vim[k] : 0.0) / a);
+        } else {
+            val[k] = (S)(vre[k] / a);
+        }
+    }
+    diag[i] = (S)((hii - b) / a);
+}
+
+// ---------------------------------------------------------------------------
+// Gershgorin bounds: exact min/max through order-preserving integer keys
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long dkey(double x)
+{
+    unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double dunkey(unsigned long long k)
+{
+    unsigned long long u = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+    return __longlong_as_double((long long)u);
+}
+__global__ void k_bounds_init(unsigned long long *keys)
+{
+    if (threadIdx.x == 0) {
+        keys[0] = dkey(INFINITY);
+        keys[1] = dkey(-INFINITY);
+    }
+}
+__global__ void k_bounds_decode(unsigned long long *keys)
+{
+    if (threadIdx.x == 0) {
+        double lo = dunkey(keys[0]), hi = dunkey(keys[1]);
+        ((double *)keys)[0] = lo;
+        ((double *)keys)[1] = hi;
+    }
+}
+__device__ __forceinline__ void bounds_commit(double lo, double hi, unsigned long long *keys)
+{
+    for (int off = 32; off > 0; off >>= 1) {
+        lo = fmin(lo, __shfl_xor(lo, off, 64));
+        hi = fmax(hi, __shfl_xor(hi, off, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMin(&keys[0], dkey(lo));
+        atomicMax(&keys[1], dkey(hi));
+    }
+}
+__global__ __launch_bounds__(256) void k_bounds_lattice(uint32_t Lx, uint32_t Ly, uint32_t Lz, int dim, int spin,
+                                                        double t, const double *onsite, const double *spinor,
+                                                        unsigned long long *keys)
+{
+    const uint32_t N = Lx * Ly * Lz;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    double lo = INFINITY, hi = -INFINITY;
+    if (i < N) {
+        const uint32_t x = i % Lx, y = (i / Lx) % Ly, z = i / (Lx * Ly);
+        const uint32_t L[3] = {Lx, Ly, Lz};
+        double rad = 0.0;
+        for (int s = 0; s < 2 * dim; ++s) {
+            if (!spin) {
+                rad = rad + fabs(t);
+            } else {
+                uint32_t c[3] = {x, y, z};
+                const int ax = s / 2;
+                c[ax] = (s & 1) ? (c[ax] + 1) % L[ax] : (c[ax] + L[ax] - 1) % L[ax];
+                const uint32_t j = c[0] + Lx * (c[1] + Ly * c[2]);
+                const double ci = spinor[3 * (size_t)i], xi = spinor[3 * (size_t)i + 1], yi = spinor[3 * (size_t)i + 2];
+                const double cj = spinor[3 * (size_t)j], xj = spinor[3 * (size_t)j + 1], yj = spinor[3 * (size_t)j + 2];
+                const double zr = ci * cj + (xi * xj + yi * yj);
+                const double zi = xi * yj - yi * xj;
+                rad = rad + hypot((-t) * zr, (-t) * zi);
+            }
+        }
+        const double eps = onsite ? onsite[i] : 0.0;
+        lo = eps - rad;
+        hi = eps + rad;
+    }
+    bounds_commit(lo, hi, keys);
+}
+__global__ __launch_bounds__(256) void k_bounds_csr(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                                                    const double *vre, const double *vim, unsigned long long *keys)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double lo = INFINITY, hi = -INFINITY;
+    if (i < n) {
+        double hii = 0.0, rad = 0.0;
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+            if (col[k] == i) hii = hii + vre[k];
+            else rad = rad + hypot(vre[k], vim ? vim[k] : 0.0);
+        }
+        lo = hii - rad;
+        hi = hii + rad;
+    }
+    bounds_commit(lo, hi, keys);
+}
+
+// ---------------------------------------------------------------------------
+// density of states, Eq. (fKPM), one thread per Chebyshev point
+// ---------------------------------------------------------------------------
+constexpr int DOS_CHUNK = 2048;
+__global__ __launch_bounds__(256) void k_dos(const double *mu, int M, int jackson, int K, double a, double b,
+                                             double *omega, double *rho)
+{
+    __shared__ double w[DOS_CHUNK];
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t step = 2 * (uint64_t)k + 1, fourK = 4 * (uint64_t)K;
+    const double inv2K = 1.0 / (2.0 * (double)K);
+    double f = 0.0;
+    uint64_t m = 0;                                   // n (2k+1) mod 4K for the current n
+    const double cq = cospi(1.0 / (double)(M + 1)), sq = sinpi(1.0 / (double)(M + 1));
+    for (int n0 = 0; n0 < M; n0 += DOS_CHUNK) {
+        const int nn = min(DOS_CHUNK, M - n0);
+        __syncthreads();
+        for (int u = threadIdx.x; u < nn; u += blockDim.x) {
+            const int n = n0 + u;
+            double g = 1.0;
+            if (jackson) {
+                const double x = (double)n / (double)(M + 1);
+                g = ((double)(M - n + 1) * cospi(x) + sinpi(x) * (cq / sq)) / (double)(M + 1);
+            }
+            w[u] = (n == 0 ? 1.0 : 2.0) * g * mu[n];
+        }
+        __syncthreads();
+        if (k < K) {
+            for (int u = 0; u < nn; ++u) {
+                f += w[u] * cospi((double)m * inv2K);
+                m += step;
+                if (m >= fourK) m -= fourK;
+                if (m >= fourK) m %= fourK;
+            }
+        }
+    }
+    if (k < K) {
+        const double th = ((double)k + 0.5) / (double)K;
+        omega[k] = a * cospi(th) + b;
+        rho[k] = f / (M_PI * sinpi(th)) / a;
+    }
+}
+
+// start vectors exported in FP64 for tests
+__global__ __launch_bounds__(256) void k_export_start(int vec, int cplx, uint64_t seed, uint64_t instance, uint32_t N,
+                                                      uint32_t R, double *out)
+{
+    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (uint64_t)N * R) return;
+    const uint32_t i = (uint32_t)(e / R), r = (uint32_t)(e % R);
+    uint64_t w[4] = {0, 0, 0, 0};
+    if (vec != VEC_UNIT) start_words(seed, instance, i, r / 4, w);
+    double re, im;
+    start_value(vec, w[r & 3], instance, N, i, r, re, im);
+    if (cplx) {
+        out[2 * e] = re;
+        out[2 * e + 1] = im;
+    } else {
+        out[e] = re;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// kernel tables by (precision, operator kind, chunks per thread)
+// ---------------------------------------------------------------------------
+typedef void (*step_fn)(const Inst *, const uint32_t *, int32_t);
+typedef void (*init_fn)(const Inst *, const uint32_t *);
+
+template <typename S, int TPT>
+step_fn step_for(int opk)
+{
+    switch (opk) {
+    case OP_REAL2: return k_step<S, OP_REAL2, TPT>;
+    case OP_REAL3: return k_step<S, OP_REAL3, TPT>;
+    case OP_SPIN2: return k_step<S, OP_SPIN2, TPT>;
+    case OP_SPIN3: return k_step<S, OP_SPIN3, TPT>;
+    case OP_CSR_R: return k_step<S, OP_CSR_R, TPT>;
+    default: return k_step<S, OP_CSR_C, TPT>;
+    }
+}
+step_fn get_step(int prec, int opk, int tpt)
+{
+    if (prec == KPM_F64) return tpt == 1 ? step_for<double, 1>(opk) : tpt == 2 ? step_for<double, 2>(opk) : step_for<double, 4>(opk);
+    return tpt == 1 ? step_for<float, 1>(opk) : tpt == 2 ? step_for<float, 2>(opk) : step_for<float, 4>(opk);
+}
+init_fn get_init(int prec, int tpt)
+{
+    if (prec == KPM_F64) return tpt == 1 ? k_init<double, 1> : tpt == 2 ? k_init<double, 2> : k_init<double, 4>;
+    return tpt == 1 ? k_init<float, 1> : tpt == 2 ? k_init<float, 2> : k_init<float, 4>;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// handles
+// ---------------------------------------------------------------------------
+struct kpm_ham {
+    int32_t kind, hop, prec, dim, opk;
+    int64_t L[3];
+    int64_t N, nnz;
+    double a, b, t;
+    int cplx_op, has_diag;
+    char *mem;
+    void *diag, *bond, *hopv, *val;
+    int64_t *row_ptr;
+    int32_t *col;
+    int *flag;
+};
+
+struct kpm_solve {
+    kpm_ham *h;
+    Inst inst;
+    char *ws;
+    Inst *tab_dev;
+    int32_t next;      // next recursion step n to run
+    int32_t written;   // dots indices [0, written) have partials
+    int32_t reduced;   // dots indices [0, reduced) are reduced
+};
+
+namespace {
+
+// Geometry of one solve: everything but device pointers.
+struct Plan {
+    int cplx;
+    uint32_t W, Rs, C, nel, tiles, nb;
+    int32_t K, P, tpt;
+    size_t esz;
+    size_t part_bytes, dots_bytes, buf_bytes;
+};
+
+bool make_plan(const kpm_ham *h, int32_t M, int32_t R, int32_t vec, Plan &p)
+{
+    if (!h || M < 1 || R < 1 || vec < 0 || vec > 2) return false;
+    p.esz = h->prec == KPM_F64 ? 8 : 4;
+    p.W = (uint32_t)(16 / p.esz);
+    p.cplx = (h->cplx_op || vec == KPM_VEC_PHASE) ? 1 : 0;
+    const uint64_t scal = (uint64_t)R * (p.cplx ? 2 : 1);
+    const uint64_t Rs = (scal + p.W - 1) / p.W * p.W;
+    const uint64_t C = Rs / p.W;
+    const uint64_t nel = (uint64_t)h->N * C;
+    if (Rs > (1u << 30) || nel >= (1ull << 31) - (1ull << 16)) return false;
+    p.Rs = (uint32_t)Rs;
+    p.C = (uint32_t)C;
+    p.nel = (uint32_t)nel;
+    p.tpt = g_tpt;
+    const uint64_t per_tile = (uint64_t)BLOCK * p.tpt;
+    p.tiles = (uint32_t)((nel + per_tile - 1) / per_tile);
+    uint32_t nb = (p.tiles + 7) / 8 * 8;
+    p.nb = std::min<uint32_t>(nb, (uint32_t)g_max_blocks);
+    p.K = M / 2;
+    p.P = std::min(p.K + 1, PSLOTS_MAX);
+    p.part_bytes = align256((size_t)p.P * p.tiles * 4 * sizeof(double));
+    p.dots_bytes = align256((size_t)(p.K + 1) * 4 * sizeof(double));
+    p.buf_bytes = align256((size_t)h->N * p.Rs * p.esz);
+    return true;
+}
+
+size_t instance_bytes(const Plan &p) { return p.part_bytes + p.dots_bytes + 2 * p.buf_bytes; }
+
+void fill_inst(const kpm_ham *h, const Plan &p, int32_t M, int32_t R, int32_t vec, uint64_t seed, uint64_t instance,
+               char *region, Inst &I)
+{
+    std::memset(&I, 0, sizeof(I));
+    I.opk = h->opk;
+    I.has_diag = h->has_diag;
+    I.Lx = (uint32_t)h->L[0];
+    I.Ly = (uint32_t)h->L[1];
+    I.Lz = (uint32_t)h->L[2];
+    I.N = (uint32_t)h->N;
+    I.fLx = make_fastdiv(I.Lx ? I.Lx : 1);
+    I.fLy = make_fastdiv(I.Ly ? I.Ly : 1);
+    I.fC = make_fastdiv(p.C);
+    I.C = p.C;
+    I.Rs = p.Rs;
+    I.nel = p.nel;
+    I.tiles = p.tiles;
+    I.nb = p.nb;
+    I.block0 = 0;
+    I.tpt = p.tpt;
+    I.cplx = p.cplx;
+    I.M = M;
+    I.K = p.K;
+    I.R = R;
+    I.vec = vec;
+    I.step0 = 0;
+    I.pslots = p.P;
+    I.seed = seed;
+    I.instance = instance;
+    I.norm = (vec == KPM_VEC_UNIT) ? (double)R : (double)h->N * (double)R;
+    I.diag = h->diag;
+    I.bond = h->bond;
+    I.hop = h->hopv;
+    I.row_ptr = h->row_ptr;
+    I.col = h->col;
+    I.val = h->val;
+    I.partial = (double *)region;
+    I.dots = (double *)(region + p.part_bytes);
+    I.buf0 = region + p.part_bytes + p.dots_bytes;
+    I.buf1 = region + p.part_bytes + p.dots_bytes + p.buf_bytes;
+    I.mu = nullptr;
+}
+
+kpm_status launch_init(int prec, int tpt, const Inst *tab, const uint32_t *map8, uint32_t blocks, hipStream_t st)
+{
+    hipLaunchKernelGGL(get_init(prec, tpt), dim3(blocks), dim3(BLOCK), 0, st, tab, map8);
+    return check_launch();
+}
+kpm_status launch_step(int prec, int opk, int tpt, const Inst *tab, const uint32_t *map8, uint32_t blocks, int32_t k,
+                       hipStream_t st)
+{
+    hipLaunchKernelGGL(get_step(prec, opk, tpt), dim3(blocks), dim3(BLOCK), 0, st, tab, map8, k);
+    return check_launch();
+}
+kpm_status launch_reduce(const Inst *tab, int32_t count, int32_t klo, int32_t nk, hipStream_t st)
+{
+    if (nk <= 0) return KPM_OK;
+    hipLaunchKernelGGL(k_reduce, dim3(nk, count), dim3(BLOCK), 0, st, tab, klo, nk);
+    return check_launch();
+}
+kpm_status launch_moments(const Inst *tab, int32_t count, int32_t Mmax, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_moments, dim3((Mmax + BLOCK - 1) / BLOCK, count), dim3(BLOCK), 0, st, tab);
+    return check_launch();
+}
+
+// Validate CSR structure on the device (synchronises `st`); flag_dev: one device int.
+kpm_status validate_csr(const kpm_ham_desc *d, int *flag_dev, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, flag_dev);
+    hipLaunchKernelGGL(k_check_rowptr, dim3((uint32_t)((d->n + 1 + 255) / 256)), dim3(256), 0, st, d->n, d->nnz,
+                       d->row_ptr_dev, flag_dev);
+    int flag = 0;
+    if (hipMemcpyAsync(&flag, flag_dev, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess) return KPM_ERR_DEVICE;
+    if (hipStreamSynchronize(st) != hipSuccess) return KPM_ERR_DEVICE;
+    if (flag) return KPM_ERR_INVALID_ARG;
+    if (d->nnz > 0) {
+        hipLaunchKernelGGL(k_check_cols, dim3((uint32_t)((d->nnz + 255) / 256)), dim3(256), 0, st, d->nnz, d->n,
+                           d->col_dev, flag_dev);
+        if (hipMemcpyAsync(&flag, flag_dev, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess) return KPM_ERR_DEVICE;
+        if (hipStreamSynchronize(st) != hipSuccess) return KPM_ERR_DEVICE;
+        if (flag) return KPM_ERR_INVALID_ARG;
+    }
+    return check_launch();
+}
+
+bool valid_desc(const kpm_ham_desc *d)
+{
+    if (!d) return false;
+    if (d->kind == KPM_SQUARE_2D || d->kind == KPM_CUBIC_3D) {
+        const int dim = d->kind == KPM_CUBIC_3D ? 3 : 2;
+        for (int k = 0; k < dim; ++k)
+            if (d->L[k] < 1 || d->L[k] >= (1ll << 31)) return false;
+        const int64_t Lz = dim == 3 ? d->L[2] : 1;
+        const double N = (double)d->L[0] * (double)d->L[1] * (double)Lz;
+        if (N >= 2147483648.0) return false;
+        if (d->hop != KPM_HOP_REAL && d->hop != KPM_HOP_SPIN) return false;
+        if (d->hop == KPM_HOP_SPIN && !d->spinor_dev) return false;
+        return std::isfinite(d->t);
+    }
+    if (d->kind == KPM_CSR) {
+        return d->n >= 1 && d->n < (1ll << 31) && d->nnz >= 0 && d->row_ptr_dev && (d->nnz == 0 || (d->col_dev && d->val_re_dev));
+    }
+    return false;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *kpm_status_string(kpm_status st)
+{
+    switch (st) {
+    case KPM_OK: return "ok";
+    case KPM_ERR_INVALID_ARG: return "invalid argument";
+    case KPM_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case KPM_ERR_DEVICE: return "HIP runtime error";
+    case KPM_ERR_BOUNDS: return "spectrum outside [-1, 1] or divergence";
+    case KPM_ERR_UNSUPPORTED: return "size not supported";
+    case KPM_ERR_WORKSPACE: return "workspace missing or too small";
+    }
+    return "unknown status";
+}
+
+kpm_status kpm_scale_from_bounds(double e_lo, double e_hi, double eps, double *a, double *b)
+{
+    if (!a || !b || !(e_hi > e_lo) || !(eps >= 0.0 && eps < 1.0) || !std::isfinite(e_lo) || !std::isfinite(e_hi))
+        return KPM_ERR_INVALID_ARG;
+    *a = (e_hi - e_lo) / (2.0 - eps);
+    *b = (e_hi + e_lo) / 2.0;
+    return KPM_OK;
+}
+
+kpm_status kpm_bounds_gershgorin(const kpm_ham_desc *d, double *bounds_dev, void *stream)
+{
+    if (!valid_desc(d) || !bounds_dev) return KPM_ERR_INVALID_ARG;
+    hipStream_t st = S(stream);
+    unsigned long long *keys = (unsigned long long *)bounds_dev;
+    if (d->kind == KPM_CSR) {
+        kpm_status v = validate_csr(d, (int *)bounds_dev, st);
+        if (v != KPM_OK) return v;
+        hipLaunchKernelGGL(k_bounds_init, dim3(1), dim3(64), 0, st, keys);
+        const uint32_t blocks = (uint32_t)((d->n + 255) / 256);
+        hipLaunchKernelGGL(k_bounds_csr, dim3(blocks), dim3(256), 0, st, d->n, d->row_ptr_dev, d->col_dev,
+                           d->val_re_dev, d->val_im_dev, keys);
+    } else {
+        const int dim = d->kind == KPM_CUBIC_3D ? 3 : 2;
+        const uint32_t Lz = dim == 3 ? (uint32_t)d->L[2] : 1u;
+        const uint64_t N = (uint64_t)d->L[0] * d->L[1] * Lz;
+        hipLaunchKernelGGL(k_bounds_init, dim3(1), dim3(64), 0, st, keys);
+        hipLaunchKernelGGL(k_bounds_lattice, dim3((uint32_t)((N + 255) / 256)), dim3(256), 0, st, (uint32_t)d->L[0],
+                           (uint32_t)d->L[1], Lz, dim, d->hop == KPM_HOP_SPIN ? 1 : 0, d->t, d->onsite_dev,
+                           d->spinor_dev, keys);
+    }
+    hipLaunchKernelGGL(k_bounds_decode, dim3(1), dim3(64), 0, st, keys);
+    return check_launch();
+}
+
+// Launch the preparation kernel(s) of H~ = (H - b)/a into the handle's memory.
+static kpm_status prep_launch(kpm_ham *h, const kpm_ham_desc *d, double a, double b, hipStream_t st)
+{
+    h->a = a;
+    h->b = b;
+    h->t = d->t;
+    const uint32_t blocks = (uint32_t)((h->N + 255) / 256);
+    if (h->kind == KPM_CSR) {
+        kpm_status v = validate_csr(d, h->flag, st);
+        if (v != KPM_OK) return v;
+        hipError_t ce = hipMemcpyAsync(h->row_ptr, d->row_ptr_dev, (size_t)(h->N + 1) * 8, hipMemcpyDeviceToDevice, st);
+        if (ce == hipSuccess && h->nnz)
+            ce = hipMemcpyAsync(h->col, d->col_dev, (size_t)h->nnz * 4, hipMemcpyDeviceToDevice, st);
+        if (ce != hipSuccess) return KPM_ERR_DEVICE;
+        if (h->prec == KPM_F64)
+            hipLaunchKernelGGL(k_prep_csr<double>, dim3(blocks), dim3(256), 0, st, h->N, d->row_ptr_dev, d->col_dev,
+                               d->val_re_dev, d->val_im_dev, a, b, (double *)h->diag, (double *)h->val, h->cplx_op);
+        else
+            hipLaunchKernelGGL(k_prep_csr<float>, dim3(blocks), dim3(256), 0, st, h->N, d->row_ptr_dev, d->col_dev,
+                               d->val_re_dev, d->val_im_dev, a, b, (float *)h->diag, (float *)h->val, h->cplx_op);
+    } else {
+        const int spin = d->hop == KPM_HOP_SPIN;
+        // d_i = (H_ii - b)/a vanishes identically when there is no on-site term and b == 0
+        h->has_diag = (d->onsite_dev != nullptr || b != 0.0) ? 1 : 0;
+        if (h->prec == KPM_F64)
+            hipLaunchKernelGGL(k_prep_lattice<double>, dim3(blocks), dim3(256), 0, st, (uint32_t)h->L[0],
+                               (uint32_t)h->L[1], (uint32_t)h->L[2], h->dim, spin, d->t, a, b, d->onsite_dev,
+                               d->spinor_dev, h->has_diag, (double *)h->diag, (double *)h->bond, (double *)h->hopv);
+        else
+            hipLaunchKernelGGL(k_prep_lattice<float>, dim3(blocks), dim3(256), 0, st, (uint32_t)h->L[0],
+                               (uint32_t)h->L[1], (uint32_t)h->L[2], h->dim, spin, d->t, a, b, d->onsite_dev,
+                               d->spinor_dev, h->has_diag, (float *)h->diag, (float *)h->bond, (float *)h->hopv);
+    }
+    return check_launch();
+}
+
+kpm_status kpm_build(const kpm_ham_desc *d, double a, double b, int32_t prec, void *stream, kpm_ham **out)
+{
+    if (!out || !valid_desc(d) || !(a > 0.0) || !std::isfinite(a) || !std::isfinite(b) ||
+        (prec != KPM_F64 && prec != KPM_F32))
+        return KPM_ERR_INVALID_ARG;
+    hipStream_t st = S(stream);
+    kpm_ham *h = new (std::nothrow) kpm_ham();
+    if (!h) return KPM_ERR_OUT_OF_MEMORY;
+    h->kind = d->kind;
+    h->hop = d->hop;
+    h->prec = prec;
+    const size_t esz = prec == KPM_F64 ? 8 : 4;
+    size_t bytes = 0;
+    if (d->kind == KPM_CSR) {
+        h->dim = 0;
+        h->N = d->n;
+        h->nnz = d->nnz;
+        h->L[0] = d->n; h->L[1] = 1; h->L[2] = 1;
+        h->cplx_op = d->val_im_dev ? 1 : 0;
+        h->opk = h->cplx_op ? OP_CSR_C : OP_CSR_R;
+        h->has_diag = 1;
+        const size_t o_diag = 0;
+        const size_t o_val = align256(o_diag + h->N * esz);
+        const size_t o_rp = align256(o_val + (size_t)h->nnz * esz * (h->cplx_op ? 2 : 1));
+        const size_t o_col = align256(o_rp + (size_t)(h->N + 1) * 8);
+        const size_t o_flag = align256(o_col + (size_t)h->nnz * 4 + 4);
+        bytes = o_flag + 256;
+        if (hipMalloc((void **)&h->mem, bytes) != hipSuccess) { delete h; return KPM_ERR_OUT_OF_MEMORY; }
+        h->diag = h->mem + o_diag;
+        h->val = h->mem + o_val;
+        h->row_ptr = (int64_t *)(h->mem + o_rp);
+        h->col = (int32_t *)(h->mem + o_col);
+        h->flag = (int *)(h->mem + o_flag);
+    } else {
+        h->dim = d->kind == KPM_CUBIC_3D ? 3 : 2;
+        h->L[0] = d->L[0];
+        h->L[1] = d->L[1];
+        h->L[2] = h->dim == 3 ? d->L[2] : 1;
+        h->N = h->L[0] * h->L[1] * h->L[2];
+        const int spin = d->hop == KPM_HOP_SPIN;
+        h->cplx_op = spin;
+        h->opk = spin ? (h->dim == 3 ? OP_SPIN3 : OP_SPIN2) : (h->dim == 3 ? OP_REAL3 : OP_REAL2);
+        const size_t o_hop = 0;
+        const size_t o_diag = 256;
+        const size_t o_bond = align256(o_diag + h->N * esz);
+        bytes = align256(o_bond + (spin ? (size_t)h->N * h->dim * 2 * esz : 0)) + 256;
+        if (hipMalloc((void **)&h->mem, bytes) != hipSuccess) { delete h; return KPM_ERR_OUT_OF_MEMORY; }
+        h->hopv = h->mem + o_hop;
+        h->diag = h->mem + o_diag;
+        h->bond = spin ? h->mem + o_bond : nullptr;
+    }
+    kpm_status s = prep_launch(h, d, a, b, st);
+    if (s != KPM_OK) {
+        (void)hipFree(h->mem);
+        delete h;
+        return s;
+    }
+    *out = h;
+    return KPM_OK;
+}
+
+kpm_status kpm_update(kpm_ham *h, const kpm_ham_desc *d, double a, double b, void *stream)
+{
+    if (!h || !valid_desc(d) || !(a > 0.0) || !std::isfinite(a) || !std::isfinite(b) || d->kind != h->kind)
+        return KPM_ERR_INVALID_ARG;
+    if (d->kind == KPM_CSR) {
+        if (d->n != h->N || d->nnz != h->nnz || (d->val_im_dev ? 1 : 0) != h->cplx_op) return KPM_ERR_INVALID_ARG;
+    } else {
+        const int dim = d->kind == KPM_CUBIC_3D ? 3 : 2;
+        if (d->L[0] != h->L[0] || d->L[1] != h->L[1] || (dim == 3 && d->L[2] != h->L[2]) || d->hop != h->hop)
+            return KPM_ERR_INVALID_ARG;
+    }
+    return prep_launch(h, d, a, b, S(stream));
+}
+
+void kpm_free(kpm_ham *h)
+{
+    if (!h) return;
+    if (h->mem) (void)hipFree(h->mem);
+    delete h;
+}
+
+int64_t kpm_ham_dim(const kpm_ham *h) { return h ? h->N : -1; }
+
+size_t kpm_workspace_bytes(const kpm_ham *h, int32_t M, int32_t R, int32_t vec)
+{
+    Plan p;
+    if (!make_plan(h, M, R, vec, p)) return 0;
+    return align256(sizeof(Inst)) + instance_bytes(p);
+}
+
+kpm_status kpm_solve_begin(kpm_ham *h, int32_t M, int32_t R, int32_t vec, uint64_t seed, uint64_t instance,
+                           void *ws, size_t ws_bytes, void *stream, kpm_solve **out)
+{
+    Plan p;
+    if (!out || !make_plan(h, M, R, vec, p)) return KPM_ERR_INVALID_ARG;
+    const size_t need = align256(sizeof(Inst)) + instance_bytes(p);
+    if (!ws || ((uintptr_t)ws & 255) || ws_bytes < need) return KPM_ERR_WORKSPACE;
+    kpm_solve *s = new (std::nothrow) kpm_solve();
+    if (!s) return KPM_ERR_OUT_OF_MEMORY;
+    hipStream_t st = S(stream);
+    s->h = h;
+    s->ws = (char *)ws;
+    s->tab_dev = (Inst *)ws;
+    fill_inst(h, p, M, R, vec, seed, instance, s->ws + align256(sizeof(Inst)), s->inst);
+    kpm_status e = upload(s->tab_dev, &s->inst, sizeof(Inst), st);
+    if (e == KPM_OK) e = launch_init(h->prec, p.tpt, s->tab_dev, nullptr, p.nb, st);
+    s->written = 1;
+    s->reduced = 0;
+    s->next = 0;
+    if (e == KPM_OK && p.K >= 1) {
+        e = launch_step(h->prec, h->opk, p.tpt, s->tab_dev, nullptr, p.nb, 0, st);
+        s->next = 1;
+        s->written = 2;
+    }
+    if (e != KPM_OK) {
+        delete s;
+        return e;
+    }
+    *out = s;
+    return KPM_OK;
+}
+
+static kpm_status solve_reduce_pending(kpm_solve *s, hipStream_t st)
+{
+    const int32_t n = s->written - s->reduced;
+    if (n <= 0) return KPM_OK;
+    // dots index idx = step0 + 1 + k with step0 = 0
+    kpm_status e = launch_reduce(s->tab_dev, 1, s->reduced - 1, n, st);
+    s->reduced = s->written;
+    return e;
+}
+
+kpm_status kpm_solve_advance(kpm_solve *s, int32_t max_steps, void *stream, int32_t *remaining)
+{
+    if (!s || max_steps < 0) return KPM_ERR_INVALID_ARG;
+    hipStream_t st = S(stream);
+    const Inst &I = s->inst;
+    kpm_status e = KPM_OK;
+    for (int32_t c = 0; c < max_steps && s->next < I.K && e == KPM_OK; ++c) {
+        if (s->written - s->reduced >= I.pslots) e = solve_reduce_pending(s, st);
+        if (e != KPM_OK) break;
+        e = launch_step(s->h->prec, I.opk, I.tpt, s->tab_dev, nullptr, I.nb, s->next, st);
+        s->next += 1;
+        s->written += 1;
+    }
+    if (e == KPM_OK && s->written - s->reduced >= I.pslots) e = solve_reduce_pending(s, st);
+    if (remaining) *remaining = I.K - s->next;
+    return e;
+}
+
+kpm_status kpm_solve_finish(kpm_solve *s, double *mu_dev, void *stream)
+{
+    if (!s || !mu_dev) return KPM_ERR_INVALID_ARG;
+    hipStream_t st = S(stream);
+    kpm_status e = KPM_OK;
+    if (s->next < s->inst.K) e = kpm_solve_advance(s, s->inst.K - s->next, stream, nullptr);
+    if (e == KPM_OK) e = solve_reduce_pending(s, st);
+    if (e != KPM_OK) return e;
+    s->inst.mu = mu_dev;
+    e = upload(s->tab_dev, &s->inst, sizeof(Inst), st);
+    if (e == KPM_OK) e = launch_moments(s->tab_dev, 1, s->inst.M, st);
+    return e;
+}
+
+void kpm_solve_free(kpm_solve *s) { delete s; }
+
+kpm_status kpm_moments(kpm_ham *h, int32_t M, int32_t R, int32_t vec, uint64_t seed, uint64_t instance, void *ws,
+                       size_t ws_bytes, double *mu_dev, void *stream)
+{
+    if (!mu_dev) return KPM_ERR_INVALID_ARG;
+    kpm_solve *s = nullptr;
+    kpm_status e = kpm_solve_begin(h, M, R, vec, seed, instance, ws, ws_bytes, stream, &s);
+    if (e != KPM_OK) return e;
+    e = kpm_solve_finish(s, mu_dev, stream);
+    kpm_solve_free(s);
+    return e;
+}
+
+// ---------------------------------------------------------------------------
+// batched solves
+// ---------------------------------------------------------------------------
+namespace {
+struct BatchLayout {
+    std::vector<Plan> plans;
+    std::vector<int> group_of;       // instance -> group
+    std::vector<int> gopk;           // group -> operator kind
+    std::vector<std::vector<int>> members;
+    std::vector<uint32_t> gblocks;   // blocks per group launch
+    size_t tab_off, map_off, inst_off, total;
+    std::vector<size_t> map_goff;    // per group offset into the map region (in uint32)
+    std::vector<size_t> region_off;  // per instance
+    int prec;
+};
+
+bool batch_layout(kpm_ham *const *h, int32_t count, const int32_t *M, const int32_t *R, int32_t vec, BatchLayout &L)
+{
+    if (!h || count < 1 || count > 65535 || !M || !R) return false;
+    L.plans.resize(count);
+    L.group_of.assign(count, -1);
+    L.prec = h[0] ? h[0]->prec : -1;
+    for (int i = 0; i < count; ++i) {
+        if (!h[i] || h[i]->prec != L.prec) return false;
+        if (!make_plan(h[i], M[i], R[i], vec, L.plans[i])) return false;
+        int g = -1;
+        for (size_t k = 0; k < L.gopk.size(); ++k)
+            if (L.gopk[k] == h[i]->opk) g = (int)k;
+        if (g < 0) {
+            g = (int)L.gopk.size();
+            L.gopk.push_back(h[i]->opk);
+            L.members.emplace_back();
+        }
+        L.group_of[i] = g;
+        L.members[g].push_back(i);
+    }
+    L.gblocks.assign(L.gopk.size(), 0);
+    L.map_goff.assign(L.gopk.size(), 0);
+    size_t map_words = 0;
+    for (size_t g = 0; g < L.gopk.size(); ++g) {
+        uint32_t b = 0;
+        for (int i : L.members[g]) b += L.plans[i].nb;
+        L.gblocks[g] = b;
+        L.map_goff[g] = map_words;
+        map_words += b / 8;
+    }
+    L.tab_off = 0;
+    L.map_off = align256((size_t)count * sizeof(Inst));
+    L.inst_off = L.map_off + align256(map_words * 4 + 4);
+    L.region_off.resize(count);
+    size_t off = L.inst_off;
+    for (int i = 0; i < count; ++i) {
+        L.region_off[i] = off;
+        off += instance_bytes(L.plans[i]);
+    }
+    L.total = off;
+    return true;
+}
+}  // namespace
+
+size_t kpm_workspace_bytes_batched(kpm_ham *const *h, int32_t count, const int32_t *M, const int32_t *R, int32_t vec)
+{
+    BatchLayout L;
+    if (!batch_layout(h, count, M, R, vec, L)) return 0;
+    return L.total;
+}
+
+kpm_status kpm_moments_batched(kpm_ham *const *h, int32_t count, const int32_t *M, const int32_t *R, int32_t vec,
+                               const uint64_t *seed, const uint64_t *instance, void *ws, size_t ws_bytes,
+                               double *const *mu_dev, void *stream)
+{
+    BatchLayout L;
+    if (!seed || !instance || !mu_dev || !batch_layout(h, count, M, R, vec, L)) return KPM_ERR_INVALID_ARG;
+    for (int i = 0; i < count; ++i)
+        if (!mu_dev[i]) return KPM_ERR_INVALID_ARG;
+    if (!ws || ((uintptr_t)ws & 255) || ws_bytes < L.total) return KPM_ERR_WORKSPACE;
+    hipStream_t st = S(stream);
+    char *base = (char *)ws;
+    std::vector<Inst> tab(count);
+    std::vector<uint32_t> map;
+    std::vector<uint32_t> gfirst(L.gopk.size());  // first table index of each group
+    // Instances are laid out in the table group by group so each group's launch
+    // sees a contiguous table and its own block map.
+    std::vector<int> order;
+    for (size_t g = 0; g < L.gopk.size(); ++g) {
+        gfirst[g] = (uint32_t)order.size();
+        for (int i : L.members[g]) order.push_back(i);
+    }
+    int32_t Kmax = 0, Mmax = 0;
+    for (size_t g = 0; g < L.gopk.size(); ++g) {
+        uint32_t blk = 0;
+        for (size_t r = 0; r < L.members[g].size(); ++r) {
+            const int i = L.members[g][r];
+            const uint32_t ti = gfirst[g] + (uint32_t)r;
+            fill_inst(h[i], L.plans[i], M[i], R[i], vec, seed[i], instance[i], base + L.region_off[i], tab[ti]);
+            tab[ti].block0 = blk;
+            tab[ti].mu = mu_dev[i];
+            for (uint32_t b = 0; b < L.plans[i].nb / 8; ++b) map.push_back(r);
+            blk += L.plans[i].nb;
+            Kmax = std::max(Kmax, L.plans[i].K);
+            Mmax = std::max(Mmax, M[i]);
+        }
+    }
+    Inst *tab_dev = (Inst *)(base + L.tab_off);
+    uint32_t *map_dev = (uint32_t *)(base + L.map_off);
+    kpm_status e = upload(tab_dev, tab.data(), tab.size() * sizeof(Inst), st);
+    if (e == KPM_OK && !map.empty()) e = upload(map_dev, map.data(), map.size() * 4, st);
+    const int tpt = L.plans[0].tpt;
+    for (size_t g = 0; g < L.gopk.size() && e == KPM_OK; ++g)
+        e = launch_init(L.prec, tpt, tab_dev + gfirst[g], map_dev + L.map_goff[g], L.gblocks[g], st);
+    int32_t written = 1, reduced = 0;  // dots indices, in lockstep for every instance
+    for (int32_t k = 0; k < Kmax && e == KPM_OK; ++k) {
+        if (written - reduced >= PSLOTS_MAX) {
+            e = launch_reduce(tab_dev, count, reduced - 1, written - reduced, st);
+            reduced = written;
+        }
+        for (size_t g = 0; g < L.gopk.size() && e == KPM_OK; ++g)
+            e = launch_step(L.prec, L.gopk[g], tpt, tab_dev + gfirst[g], map_dev + L.map_goff[g], L.gblocks[g], k, st);
+        written += 1;
+    }
+    if (e == KPM_OK) e = launch_reduce(tab_dev, count, reduced - 1, written - reduced, st);
+    if (e == KPM_OK) e = launch_moments(tab_dev, count, Mmax, st);
+    return e;
+}
+
+kpm_status kpm_dos(const double *mu_dev, int32_t M, int32_t jackson, int32_t K, double a, double b, double *omega_dev,
+                   double *rho_dev, void *stream)
+{
+    if (!mu_dev || !omega_dev || !rho_dev || M < 1 || K < 1 || !(a > 0.0) || !std::isfinite(b)) return KPM_ERR_INVALID_ARG;
+    hipLaunchKernelGGL(k_dos, dim3((K + 255) / 256), dim3(256), 0, S(stream), mu_dev, M, jackson ? 1 : 0, K, a, b,
+                       omega_dev, rho_dev);
+    return check_launch();
+}
+
+kpm_status kpm_start_vectors(int32_t vec, int32_t complex_layout, uint64_t seed, uint64_t instance, int64_t N, int32_t R,
+                             double *out_dev, void *stream)
+{
+    if (!out_dev || vec < 0 || vec > 2 || N < 1 || R < 1 || N >= (1ll << 31) || (double)N * R >= 4.0e9)
+        return KPM_ERR_INVALID_ARG;
+    const uint64_t n = (uint64_t)N * R;
+    const int cplx = (complex_layout || vec == KPM_VEC_PHASE) ? 1 : 0;
+    hipLaunchKernelGGL(k_export_start, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, S(stream), vec, cplx, seed,
+                       instance, (uint32_t)N, (uint32_t)R, out_dev);
+    return check_launch();
+}
+
+kpm_status kpm_set_launch(int32_t elems_per_thread, int32_t max_blocks)
+{
+    if (elems_per_thread != 0 && elems_per_thread != 1 && elems_per_thread != 2 && elems_per_thread != 4)
+        return KPM_ERR_INVALID_ARG;
+    if (max_blocks != 0 && (max_blocks < 8 || (max_blocks % 8) != 0)) return KPM_ERR_INVALID_ARG;
+    if (elems_per_thread) g_tpt = elems_per_thread;
+    if (max_blocks) g_max_blocks = max_blocks;
+    return KPM_OK;
+}
+
+kpm_status kpm_get_launch(int32_t *elems_per_thread, int32_t *max_blocks)
+{
+    if (!elems_per_thread || !max_blocks) return KPM_ERR_INVALID_ARG;
+    *elems_per_thread = g_tpt;
+    *max_blocks = g_max_blocks;
+    return KPM_OK;
+}
+
+// Host-side self-check of the division-by-constant helper (used by CPU tests).
+int32_t kpm_selftest_fastdiv(uint32_t d, const uint32_t *n, int32_t count)
+{
+    if (d == 0) return -1;
+    FastDiv f = make_fastdiv(d);
+    for (int32_t k = 0; k < count; ++k)
+        if (fdiv(n[k], f) != n[k] / d) return k + 1;
+    return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,55 @@
+"""Shared helpers for the GPU tests: run a case through the C ABI and through the oracle."""
+import numpy as np
+
+import oracle
+import paper_1105_5481_amd as kpm
+from paper_1105_5481_amd import workloads as wl
+
+# FP64 parity (the spec bar): |mu_gpu - mu_oracle| <= REL64 * max(|mu_oracle|, FLOOR64).
+# Both sides evaluate the same vectors with the same per-element operation order and
+# double-double dots; the floor only guards moments that are zero up to rounding.
+REL64 = 1e-12
+FLOOR64 = 1e-9
+# FP32 recursion with FP64 accumulation: absolute error per moment.
+ABS32 = 1e-5
+
+
+def oracle_moments(op, a, b, M, R, vec, seed, instance=0, formula_a=False):
+    if isinstance(op, wl.CSR):
+        return oracle.moments_csr(op.row_ptr, op.col, op.val_re, op.val_im, a, b, M, R, vec_kind=vec, seed=seed,
+                                  instance=instance, formula_a=formula_a)
+    return oracle.moments_lattice(op.dim, op.L[:op.dim], op.t, a, b, M, R, vec_kind=vec, seed=seed,
+                                  instance=instance, hop=op.hop, onsite=op.onsite, spinor=op.spinor,
+                                  formula_a=formula_a)
+
+
+def oracle_bounds(op):
+    if isinstance(op, wl.CSR):
+        return oracle.gershgorin_csr(op.row_ptr, op.col, op.val_re, op.val_im)
+    return oracle.gershgorin_lattice(op.dim, op.L[:op.dim], op.t, op.hop, op.onsite, op.spinor)
+
+
+def gpu_moments(op, a, b, prec, M, R, vec, seed, instance=0):
+    h = kpm.Hamiltonian(op, a, b, prec)
+    mu = kpm.moments(h, M, R, vec, seed, instance)
+    out = mu.cpu().numpy()
+    h.free()
+    return out
+
+
+def fp64_report(gpu, ref):
+    d = np.abs(gpu - ref)
+    rel = d / np.maximum(np.abs(ref), FLOOR64)
+    return float(d.max()), float(rel.max()), int(np.count_nonzero(gpu != ref))
+
+
+def assert_fp64(gpu, ref, what=""):
+    dmax, rmax, ndiff = fp64_report(gpu, ref)
+    print(f"  fp64 {what}: max|d|={dmax:.3e} max rel={rmax:.3e} differing={ndiff}/{len(ref)}", flush=True)
+    assert rmax <= REL64, (what, dmax, rmax)
+
+
+def assert_fp32(gpu, ref, what=""):
+    dmax = float(np.abs(gpu - ref).max())
+    print(f"  fp32 {what}: max|d|={dmax:.3e}", flush=True)
+    assert dmax <= ABS32, (what, dmax)

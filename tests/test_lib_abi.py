@@ -1,0 +1,105 @@
+"""The C ABI library loads and exports every entry point include/kpm.h declares; host-only logic.
+
+No test here launches a kernel: every call below either is pure host arithmetic or is rejected
+by argument validation before any HIP call.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1105_5481_amd as kpm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "kpm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(kpm_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1105_5481_amd import build
+    if not os.path.exists(build.LIB):
+        build.build()
+    return kpm.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = declared_symbols()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_status_strings(L):
+    for st in range(7):
+        assert L.kpm_status_string(st).decode()
+    assert L.kpm_status_string(99).decode() == "unknown status"
+
+
+def test_scale_from_bounds(L):
+    a, b = kpm.scale_from_bounds(-6.0, 6.0, 0.01)
+    assert a == 12.0 / 1.99 and b == 0.0
+    a, b = kpm.scale_from_bounds(-1.0, 3.0, 0.0)
+    assert (a, b) == (2.0, 1.0)
+    for bad in [(1.0, 1.0, 0.01), (2.0, 1.0, 0.0), (-1.0, 1.0, 1.0), (-1.0, 1.0, -0.1), (float("nan"), 1.0, 0.0)]:
+        with pytest.raises(kpm.KPMError):
+            kpm.scale_from_bounds(*bad)
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 5, 7, 8, 9, 10, 16, 31, 48, 63, 64, 96, 100, 1000, 4096, 65537,
+                               2**20 + 3, 2**31 - 1, 2**31, 2**32 - 1])
+def test_fast_division(L, d):
+    g = np.random.default_rng(d)
+    n = np.concatenate([np.arange(0, 2000, dtype=np.uint32), g.integers(0, 2**32, 20000, dtype=np.uint64).astype(np.uint32),
+                        np.array([2**32 - 1, 2**32 - 2, 2**31, 2**31 - 1, d, d - 1, d + 1, 2 * d - 1], dtype=np.uint64).astype(np.uint32)])
+    n = np.ascontiguousarray(n)
+    r = L.kpm_selftest_fastdiv(ctypes.c_uint32(d), n.ctypes.data_as(ctypes.c_void_p), len(n))
+    assert r == 0, (d, int(n[r - 1]) if r > 0 else None)
+
+
+def test_argument_validation_without_device(L):
+    # NULL descriptor / handle and out-of-range sizes are rejected before any HIP call
+    h = ctypes.c_void_p()
+    assert L.kpm_build(None, 1.0, 0.0, 0, None, ctypes.byref(h)) == 1
+    assert L.kpm_workspace_bytes(None, 16, 4, 0) == 0
+    assert L.kpm_moments(None, 16, 4, 0, 1, 0, None, 0, None, None) != 0
+    assert L.kpm_dos(None, 16, 1, 64, 1.0, 0.0, None, None, None) == 1
+    assert L.kpm_start_vectors(5, 0, 0, 0, 10, 2, None, None) == 1
+    assert L.kpm_set_launch(3, 0) == 1
+    assert L.kpm_set_launch(0, 12) == 1
+    d = kpm.HamDesc()
+    d.kind = 3
+    d.L[0], d.L[1], d.L[2] = 4, 0, 4             # zero extent
+    assert L.kpm_build(ctypes.byref(d), 1.0, 0.0, 0, None, ctypes.byref(h)) == 1
+    d.L[1] = 4
+    assert L.kpm_build(ctypes.byref(d), -1.0, 0.0, 0, None, ctypes.byref(h)) == 1   # a <= 0
+    assert L.kpm_build(ctypes.byref(d), 1.0, 0.0, 7, None, ctypes.byref(h)) == 1    # bad precision
+    d.hop = 1                                     # spin hopping without spinors
+    assert L.kpm_build(ctypes.byref(d), 1.0, 0.0, 0, None, ctypes.byref(h)) == 1
+    d.kind = 7
+    assert L.kpm_bounds_gershgorin(ctypes.byref(d), None, None) == 1
+
+
+def test_launch_settings_roundtrip(L):
+    old = kpm.get_launch()
+    try:
+        kpm.set_launch(2, 1024)
+        assert kpm.get_launch() == (2, 1024)
+        kpm.set_launch(0, 0)
+        assert kpm.get_launch() == (2, 1024)
+    finally:
+        kpm.set_launch(*old)
+
+
+def test_no_cpu_fallback_when_library_missing(monkeypatch):
+    """The product path raises instead of computing anything without the HIP library."""
+    monkeypatch.setattr(kpm, "_lib", None)
+    monkeypatch.setattr(kpm, "_LIB_PATH", "/nonexistent/libkpm.so")
+    with pytest.raises(kpm.KPMError):
+        kpm.lib()
