@@ -27,6 +27,12 @@ if ROOT not in sys.path:
 METRIC = "site·moment·vector updates/s + % HBM peak; p50/p99 solve latency vs plain FP64"
 UNIT = "site·moment·vector updates/s"
 HBM_PEAK_GBS = 8000.0
+WORKLOAD_TEXT = {
+    "config2": "3D cubic 64^3 periodic lattice, spin hopping from seeded spins uniform on the sphere, M=1024 "
+               "moments, R=32 random-phase vectors, complex64 recursion, FP64 moments, Jackson DoS on 2048 points",
+    "config4": "2D square 2048^2 periodic lattice, Anderson disorder uniform[-1,1], M=4096 moments, R=64 +-1 "
+               "vectors, FP32 recursion, FP64 moments, Jackson DoS on 8192 points",
+}
 
 
 def log(msg):
@@ -39,6 +45,44 @@ def algorithmic_bytes_per_step(N, R, cplx, esz, has_diag, bonds_per_site):
     e = esz * (2 if cplx else 1)
     meta = N * ((esz if has_diag else 0) + bonds_per_site * 2 * esz)
     return 3 * N * R * e + meta
+
+
+def kernel_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kpm_kernels.hpp", "kpm_device.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_1105_5481_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed counter record, or None when the
+    kernel source has changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        rec = json.load(open(path)).get(workload, {})
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel") != kernel or rec.get("source_digest") != kernel_source_digest():
+        return None
+    return rec["fetch_kib"] * 1024 * rec["fetch_factor"] + rec["write_kib"] * 1024 * rec["write_factor"]
+
+
+def pmc_summary(root):
+    import csv
+    import collections
+    agg = collections.defaultdict(lambda: collections.defaultdict(list))
+    for dirpath, _, files in os.walk(root):
+        for f in files:
+            if f.endswith("counter_collection.csv"):
+                for r in csv.DictReader(open(os.path.join(dirpath, f))):
+                    name = r["Kernel_Name"]
+                    key = (name[:100], r["Grid_Size"])
+                    agg[key][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    print(f"kernel_source_digest {kernel_source_digest()}")
+    for (name, grid), d in sorted(agg.items()):
+        vals = "  ".join(f"{c}={sum(v) / len(v):.6g} (n={len(v)})" for c, v in sorted(d.items()))
+        print(f"{name} grid={grid}: {vals}")
 
 
 def cpu_baseline(lat, a, b, vec, seed):
@@ -65,7 +109,19 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--tpt", type=int, default=0, help="chunks per thread per tile (1, 2, 4)")
     ap.add_argument("--max-blocks", type=int, default=0)
+    ap.add_argument("--march", type=int, default=-1, help="1: march kernels for lattices, 0: flat kernels")
+    ap.add_argument("--march-items", type=int, default=0)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first run a plain 1 GiB device copy three times (counter calibration under rocprofv3)")
+    ap.add_argument("--pmc-summary", metavar="DIR",
+                    help="print per-kernel averages of rocprofv3 --pmc CSV files found under DIR and exit")
+    ap.add_argument("--workload", default="config2", choices=["config2", "config4"],
+                    help="config2 (the measured workload) or config4 (2D 2048^2, R=64, real FP32) for exploration")
     args = ap.parse_args()
+
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary)
+        return
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -80,13 +136,21 @@ def main():
         log("bench.py: no GPU visible")
         sys.exit(1)
     kpm.lib()
-    if args.tpt or args.max_blocks:
-        kpm.set_launch(args.tpt, args.max_blocks)
+    if args.calib_copy:
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.zeros_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
+    kpm.set_launch(elems_per_thread=args.tpt or None, max_blocks=args.max_blocks or None,
+                   march=None if args.march < 0 else args.march, march_items=args.march_items or None)
     dev = "cuda"
     stream = torch.cuda.current_stream()
 
-    cfg = wl.config2()
+    cfg = wl.config2() if args.workload == "config2" else wl.config4()
     lat, M, R, vec, seed = cfg["lattice"], cfg["M"], cfg["R"], cfg["vec"], cfg["seed"]
+    cplx = lat.hop == wl.HOP_SPIN or vec == wl.VEC_PHASE
     K_dos = 2 * M
     N = lat.N
     log(f"bench: workload {cfg['name']} N={N} M={M} R={R}")
@@ -147,21 +211,26 @@ def main():
     value = updates / (dt32 / args.steps)
     nrec = K - 1
     step_us = rec32 * 1e3 / nrec
-    bytes_step = algorithmic_bytes_per_step(N, R, True, 4, s32[0].b != 0.0 or lat.onsite is not None, 3)
+    bonds = lat.dim if lat.hop == wl.HOP_SPIN else 0
+    mode = "march" if kpm.get_launch()["march"] else "flat"
+    kernel_name = "k_step_%s<float, %s>" % (mode, "OP_SPIN3" if bonds else "OP_REAL2")
+    bytes_step = algorithmic_bytes_per_step(N, R, cplx, 4, s32[0].b != 0.0 or lat.onsite is not None, bonds)
     achieved = bytes_step / (step_us * 1e-6) / 1e9
+    # same start vectors for the c64 / c128 comparison
+    run_step(s32, 0)
     mu32 = s32[3].cpu().numpy()
 
     out = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "c64", "data": "synthetic",
-        "config": {"workload": "3D cubic 64^3 periodic lattice, spin hopping from seeded spins uniform on the "
-                               "sphere, M=1024 moments, R=32 random-phase vectors, complex64 recursion, FP64 "
-                               "moments, Jackson DoS on 2048 points",
-                   "N": N, "M": M, "R": R, "recursion": "complex64", "moments": "fp64"},
+        "dtype": "c64" if cplx else "f32", "data": "synthetic",
+        "config": {"workload": WORKLOAD_TEXT[args.workload],
+                   "N": N, "M": M, "R": R, "recursion": "complex64" if cplx else "float32", "moments": "fp64"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_step<float, OP_SPIN3>", "bytes_per_launch": bytes_step,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(args.workload, kernel_name),
+                     "kernel": kernel_name,
+                     "bytes_per_launch": bytes_step,
                      "avg_launch_us": step_us},
     }
 
@@ -169,11 +238,12 @@ def main():
         s64 = make_solver(kpm.F64)
         dt64, rec64 = timed(s64, args.fp64_steps, 1, "c128")
         v64 = updates / (dt64 / args.fp64_steps)
+        run_step(s64, 0)
         mu64 = s64[3].cpu().numpy()
         import numpy as np
         out["fp64_path"] = {"value": v64, "unit": UNIT, "ms_per_step": dt64 / args.fp64_steps * 1e3,
-                            "dtype": "c128", "speedup_c64_over_c128": value / v64,
-                            "c64_max_abs_err_vs_c128": float(np.abs(mu32 - mu64).max())}
+                            "dtype": "c128" if cplx else "f64", "speedup_fp32_over_fp64": value / v64,
+                            "fp32_max_abs_err_vs_fp64": float(np.abs(mu32 - mu64).max())}
         s64[0].free()
 
     if not args.no_cpu_baseline:

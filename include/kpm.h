@@ -190,14 +190,26 @@ kpm_status kpm_start_vectors(int32_t vec, int32_t complex_layout, uint64_t seed,
                              uint64_t instance, int64_t N, int32_t R, double *out_dev,
                              void *stream);
 
-/* Launch-shape tuning (host state, process-wide): elements per thread per tile
- * (1, 2 or 4) and the maximum blocks per launch for one instance (multiple of
- * 8).  Values of 0 keep the current setting.  Results do not depend on them
- * except through the reduction order of the per-tile partials; they are fixed
- * per tile, so any setting gives bitwise-identical moments for a given
- * elements-per-thread value. */
-kpm_status kpm_set_launch(int32_t elems_per_thread, int32_t max_blocks);
-kpm_status kpm_get_launch(int32_t *elems_per_thread, int32_t *max_blocks);
+/* Launch-shape tuning (host state, process-wide; applies to solves begun
+ * afterwards).  Keys:
+ *   KPM_LAUNCH_ELEMS_PER_THREAD  flat kernels: 16-byte chunks per thread per tile (1, 2 or 4)
+ *   KPM_LAUNCH_MAX_BLOCKS        blocks per instance per launch (multiple of 8, >= 8)
+ *   KPM_LAUNCH_MARCH             1: lattices use the march kernels; 0: the flat kernels
+ *   KPM_LAUNCH_MARCH_ITEMS       target work items per instance when the march axis is cut
+ *                                into segments (fewer items -> longer segments)
+ * The partial sums of the dot products are formed per work item, so the
+ * moments do not depend on the grid (MAX_BLOCKS) nor on the batch an instance
+ * runs in; the other keys change the work items and with them the order in
+ * which rounding errors of the dot products are summed (well below 1e-15
+ * relative).  Unknown keys or values return KPM_ERR_INVALID_ARG. */
+typedef enum {
+    KPM_LAUNCH_ELEMS_PER_THREAD = 0,
+    KPM_LAUNCH_MAX_BLOCKS = 1,
+    KPM_LAUNCH_MARCH = 2,
+    KPM_LAUNCH_MARCH_ITEMS = 3
+} kpm_launch_key;
+kpm_status kpm_set_launch(int32_t key, int32_t value);
+kpm_status kpm_get_launch(int32_t key, int32_t *value);
 
 #ifdef __cplusplus
 }

@@ -72,7 +72,7 @@ def lib():
         "kpm_dos": (i32, [P, i32, i32, i32, f64, f64, P, P, P]),
         "kpm_start_vectors": (i32, [i32, i32, u64, u64, i64, i32, P, P]),
         "kpm_set_launch": (i32, [i32, i32]),
-        "kpm_get_launch": (i32, [P, P]),
+        "kpm_get_launch": (i32, [i32, P]),
         "kpm_selftest_fastdiv": (i32, [ctypes.c_uint32, P, i32]),
     }
     for name, (res, args) in sigs.items():
@@ -320,11 +320,38 @@ def start_vectors(vec: int, complex_layout: bool, seed: int, instance: int, N: i
     return out
 
 
-def set_launch(elems_per_thread: int = 0, max_blocks: int = 0):
-    _check(lib().kpm_set_launch(elems_per_thread, max_blocks), "kpm_set_launch")
+LAUNCH_ELEMS_PER_THREAD, LAUNCH_MAX_BLOCKS, LAUNCH_MARCH, LAUNCH_MARCH_ITEMS = 0, 1, 2, 3
+_LAUNCH_KEYS = {"elems_per_thread": 0, "max_blocks": 1, "march": 2, "march_items": 3}
 
 
-def get_launch():
-    a, b = ctypes.c_int32(), ctypes.c_int32()
-    _check(lib().kpm_get_launch(ctypes.byref(a), ctypes.byref(b)), "kpm_get_launch")
-    return a.value, b.value
+def set_launch(**kw):
+    """Launch-shape tuning, e.g. set_launch(max_blocks=4096, march=1, march_items=2048)."""
+    for k, v in kw.items():
+        if v is None:
+            continue
+        _check(lib().kpm_set_launch(_LAUNCH_KEYS[k], int(v)), f"kpm_set_launch({k}={v})")
+
+
+def get_launch() -> dict:
+    out = {}
+    for k, key in _LAUNCH_KEYS.items():
+        v = ctypes.c_int32()
+        _check(lib().kpm_get_launch(key, ctypes.byref(v)), "kpm_get_launch")
+        out[k] = v.value
+    return out
+
+
+class launch_settings:
+    """Context manager applying set_launch(**kw) and restoring the previous settings."""
+
+    def __init__(self, **kw):
+        self.kw = kw
+
+    def __enter__(self):
+        self.old = get_launch()
+        set_launch(**self.kw)
+        return self
+
+    def __exit__(self, *exc):
+        set_launch(**self.old)
+        return False

@@ -4,43 +4,63 @@
 //     r_{n+1} = 2 H~ r_n - r_{n-1},  written over r_{n-1},
 // with the two dot products <r_{n+1}|r_{n+1}> and Re<r_{n+1}|r_n> that the
 // doubling identities turn into mu_{2n+2} and mu_{2n+1}, taken from registers
-// in the same pass.  Vectors are stored site-major: the R vectors (or 2R
-// interleaved re/im scalars) of site i are contiguous, padded to 16 bytes, so
-// one thread moves one 16-byte chunk of one site per stream and a wavefront
-// reads whole cache lines; the neighbours of a site are the same chunk of the
-// neighbouring sites.
+// in the same pass.
 //
-// Work is cut into tiles of 256*TPT chunks.  Each tile leaves one reduction
-// partial (FP64 sums of its dot products) in a ring of per-step slots; a
-// separate kernel later sums the partials of a step over the tiles in a fixed
-// order.  Results therefore do not depend on the launch grid or on which other
-// instances share the launch.  The blocks of one instance walk its tiles in a
-// band per XCD: block b (b mod 8 = its XCD under round-robin dispatch) covers
-// tiles of the b-th eighth of the instance, so neighbouring rows/planes are
-// read by blocks of the same XCD and hit its L2.
+// Layout.  Vectors are stored site-major: the R vectors (or 2R interleaved
+// re/im scalars) of site i are contiguous, padded to a multiple of 16 bytes
+// ("chunks").  A thread moves one 16-byte chunk per stream; a wavefront reads
+// whole cache lines, and the neighbour of a site is the same chunk of the
+// neighbouring site.
+//
+// March kernels (lattices).  The slowest lattice axis (y in 2D, z in 3D) is
+// the march axis; a "plane" is the set of sites with one march coordinate and
+// a "column" is one in-plane position.  A thread owns one chunk of one column
+// and walks a segment of S planes, keeping the chunk of planes m-1, m, m+1 in
+// registers: each vector element of r_n is fetched once per step from HBM
+// (plus two halo planes per segment).  In-plane neighbours are read through
+// L1/L2 from the adjacent columns, which neighbouring lanes and blocks of the
+// same XCD load in the same pass.
+//
+// Flat kernels (CSR, and lattices on request).  Work is cut into tiles of
+// 256*TPT consecutive chunks; every neighbour is loaded through the caches.
+//
+// Reductions.  Each work item (march: column tile x segment; flat: tile) of a
+// step leaves one partial (FP64 sums of its dot products) in a ring of
+// per-step slots; a separate kernel sums the partials of a step over the items
+// in a fixed order.  Results therefore do not depend on the launch grid or on
+// which other instances share the launch.  The blocks of one instance walk
+// its items per XCD (block b runs on XCD b mod 8 under round-robin dispatch):
+// XCD x owns the x-th eighth of the column tiles (march) or tiles (flat).
 #pragma once
 
 #include "kpm_device.hpp"
+
+#define KPM_GLOBAL __attribute__((address_space(1)))
 
 namespace kpm {
 
 enum OpKind { OP_REAL2 = 0, OP_REAL3 = 1, OP_SPIN2 = 2, OP_SPIN3 = 3, OP_CSR_R = 4, OP_CSR_C = 5, OP_COUNT = 6 };
 enum { VEC_RADEMACHER = 0, VEC_PHASE = 1, VEC_UNIT = 2 };
+enum { MODE_FLAT = 0, MODE_MARCH = 1 };
 constexpr int BLOCK = 256;
+constexpr uint32_t XCD_MIN_ITEMS = 64;   // below this an instance's items are not split per XCD
 
 // One solve inside a launch (device-resident table entry).
 struct Inst {
     int32_t opk;
     int32_t has_diag;
+    int32_t mode;
+    int32_t xcd;       // items split per XCD
     uint32_t Lx, Ly, Lz, N;
     FastDiv fLx, fLy, fC;
     uint32_t C;        // 16-byte chunks per site
     uint32_t Rs;       // scalars per site (C * W)
     uint32_t nel;      // N * C
-    uint32_t tiles;    // ceil(nel / (256 * TPT))
+    uint32_t tiles;    // work items per step (= partials per step)
     uint32_t nb;       // blocks given to this instance (multiple of 8)
     uint32_t block0;   // first block of this instance in the grid (multiple of 8)
-    int32_t tpt;
+    int32_t tpt;       // flat: chunks per thread per tile
+    uint32_t P, Lm, S, nct, nseg;  // march: plane size, march extent, segment, column tiles, segments
     int32_t cplx;      // data stored as interleaved complex
     int32_t M, K, R, vec;
     int32_t step0;     // recursion step n = step0 + (launch offset k)
@@ -57,6 +77,42 @@ struct Inst {
     double *partial;   // [pslots][tiles][4]
     double *dots;      // [K+1][4] = (nn.hi, nn.lo, nm.hi, nm.lo)
     double *mu;        // [M]
+};
+
+// ---------------------------------------------------------------------------
+// global-memory access with a uniform base and a 32-bit (or, for buffers of
+// 4 GiB and more, 64-bit) byte offset
+// ---------------------------------------------------------------------------
+template <typename S, bool WIDE> struct Mem {
+    typedef typename V16<S>::T T;
+    typedef S S2 __attribute__((ext_vector_type(2)));
+    static __device__ __forceinline__ const KPM_GLOBAL char *at(const void *b, uint32_t chunk)
+    {
+        if (WIDE) return (const KPM_GLOBAL char *)b + ((uint64_t)chunk << 4);
+        return (const KPM_GLOBAL char *)b + (chunk << 4);
+    }
+    static __device__ __forceinline__ T ld(const void *b, uint32_t chunk) { return *(const KPM_GLOBAL T *)at(b, chunk); }
+    static __device__ __forceinline__ T ld_nt(const void *b, uint32_t chunk)
+    {
+        return __builtin_nontemporal_load((const KPM_GLOBAL T *)at(b, chunk));
+    }
+    static __device__ __forceinline__ void st_nt(void *b, uint32_t chunk, T v)
+    {
+        __builtin_nontemporal_store(v, (KPM_GLOBAL T *)at(b, chunk));
+    }
+    static __device__ __forceinline__ void st(void *b, uint32_t chunk, T v) { *(KPM_GLOBAL T *)at(b, chunk) = v; }
+    // element e of an array of S
+    static __device__ __forceinline__ S lds(const void *b, uint32_t e)
+    {
+        if (WIDE) return *(const KPM_GLOBAL S *)((const KPM_GLOBAL char *)b + (uint64_t)e * sizeof(S));
+        return *(const KPM_GLOBAL S *)((const KPM_GLOBAL char *)b + e * (uint32_t)sizeof(S));
+    }
+    // complex element e of an array of S pairs
+    static __device__ __forceinline__ S2 ldc(const void *b, uint32_t e)
+    {
+        if (WIDE) return *(const KPM_GLOBAL S2 *)((const KPM_GLOBAL char *)b + (uint64_t)e * (2 * sizeof(S)));
+        return *(const KPM_GLOBAL S2 *)((const KPM_GLOBAL char *)b + e * (uint32_t)(2 * sizeof(S)));
+    }
 };
 
 // ---------------------------------------------------------------------------
@@ -189,6 +245,36 @@ __device__ __forceinline__ void block_reduce_store(double x0, double x1, double 
 }
 
 // ---------------------------------------------------------------------------
+// mapping of an instance's blocks to its work items
+// ---------------------------------------------------------------------------
+// Items [0, count) of this instance handled by the block: first, stride, end,
+// and the offset that turns a local index into the item number.  With the XCD
+// split, XCD x handles the x-th eighth of the "unit" range (column tiles or
+// tiles) for every segment; `per` is the number of units.
+struct ItemRange {
+    uint32_t first, stride, count, ub, nu;   // local items [first, count) step stride; units [ub, ub+nu)
+};
+__device__ __forceinline__ ItemRange item_range(const Inst &I, uint32_t units, uint32_t segs)
+{
+    const uint32_t bl = blockIdx.x - I.block0;
+    ItemRange r;
+    if (I.xcd) {
+        const uint32_t x8 = bl & 7u;
+        r.ub = (uint32_t)(((uint64_t)units * x8) >> 3);
+        r.nu = (uint32_t)(((uint64_t)units * (x8 + 1)) >> 3) - r.ub;
+        r.first = bl >> 3;
+        r.stride = I.nb >> 3;
+    } else {
+        r.ub = 0;
+        r.nu = units;
+        r.first = bl;
+        r.stride = I.nb;
+    }
+    r.count = r.nu * segs;
+    return r;
+}
+
+// ---------------------------------------------------------------------------
 // start vectors
 // ---------------------------------------------------------------------------
 // The four Philox words for site i and vectors 4*rq .. 4*rq+3.
@@ -216,186 +302,310 @@ __device__ __forceinline__ void start_value(int vec, uint64_t word, uint64_t ins
     }
 }
 
-template <typename S, int TPT>
-__global__ __launch_bounds__(BLOCK) void k_init(const Inst *__restrict__ tab, const uint32_t *__restrict__ map8)
+// Chunk c of site i of the start block.
+template <typename S>
+__device__ __forceinline__ typename V16<S>::T start_chunk(const Inst &I, uint32_t i, uint32_t c)
 {
     typedef typename V16<S>::T T;
     constexpr int W = V16<S>::W;
-    const uint32_t h = map8 ? map8[blockIdx.x >> 3] : 0u;
-    const Inst *I = tab + h;
-    if (I->step0 != 0) return;
-    const uint32_t bl = blockIdx.x - I->block0;
-    const uint32_t x8 = bl & 7u, j = bl >> 3, q = I->nb >> 3;
-    const uint32_t tiles = I->tiles;
-    const uint32_t tb = (uint32_t)(((uint64_t)tiles * x8) >> 3);
-    const uint32_t te = (uint32_t)(((uint64_t)tiles * (x8 + 1)) >> 3);
-    S *out = (S *)I->buf0;
-    double *part = I->partial;     // slot 0
-    for (uint32_t t = tb + j; t < te; t += q) {
-        Dots<S> acc;
+    const uint32_t k0 = c * W;                  // first scalar of the chunk
+    const uint32_t r0 = I.cplx ? k0 / 2 : k0;   // first vector of the chunk (all in one Philox block)
+    uint64_t w[4] = {0, 0, 0, 0};
+    if (I.vec != VEC_UNIT) start_words(I.seed, I.instance, i, r0 / 4, w);
+    T v;
+    if (I.cplx) {
 #pragma unroll
-        for (int u = 0; u < TPT; ++u) {
-            const uint32_t e = t * (uint32_t)(BLOCK * TPT) + (uint32_t)(u * BLOCK) + threadIdx.x;
-            if (e < I->nel) {
-                const uint32_t i = fdiv(e, I->fC);
-                const uint32_t c = e - i * I->C;
-                const uint32_t k0 = c * W;                    // first scalar of the chunk
-                const uint32_t r0 = I->cplx ? k0 / 2 : k0;    // first vector of the chunk
-                uint64_t w[4] = {0, 0, 0, 0};
-                if (I->vec != VEC_UNIT) start_words(I->seed, I->instance, i, r0 / 4, w);
-                T v;
-                if (I->cplx) {
-#pragma unroll
-                    for (int l = 0; l < W / 2; ++l) {
-                        const uint32_t r = r0 + l;
-                        double re = 0.0, im = 0.0;
-                        if (r < (uint32_t)I->R) start_value(I->vec, w[r & 3], I->instance, I->N, i, r, re, im);
-                        v[2 * l] = (S)re;
-                        v[2 * l + 1] = (S)im;
-                    }
-                } else {
-#pragma unroll
-                    for (int l = 0; l < W; ++l) {
-                        const uint32_t r = r0 + l;
-                        double re = 0.0, im = 0.0;
-                        if (r < (uint32_t)I->R) start_value(I->vec, w[r & 3], I->instance, I->N, i, r, re, im);
-                        v[l] = (S)re;
-                    }
-                }
-                *reinterpret_cast<T *>(out + (size_t)i * I->Rs + k0) = v;
-                acc.norm_only(v);
-            }
+        for (int l = 0; l < W / 2; ++l) {
+            const uint32_t r = r0 + l;
+            double re = 0.0, im = 0.0;
+            if (r < (uint32_t)I.R) start_value(I.vec, w[r & 3], I.instance, I.N, i, r, re, im);
+            v[2 * l] = (S)re;
+            v[2 * l + 1] = (S)im;
         }
-        block_reduce_store<Dots<S>::DD>(acc.s0, acc.c0, acc.s1, acc.c1, part + (size_t)t * 4);
+    } else {
+#pragma unroll
+        for (int l = 0; l < W; ++l) {
+            const uint32_t r = r0 + l;
+            double re = 0.0, im = 0.0;
+            if (r < (uint32_t)I.R) start_value(I.vec, w[r & 3], I.instance, I.N, i, r, re, im);
+            v[l] = (S)re;
+        }
+    }
+    return v;
+}
+
+// r_0 into buf0 and the partials of <r_0|r_0>, over the same work items as the
+// recursion step of the instance's mode.
+template <typename S, bool WIDE>
+__global__ __launch_bounds__(BLOCK) void k_init(const Inst *__restrict__ tab, const uint32_t *__restrict__ map8)
+{
+    typedef Mem<S, WIDE> G;
+    const uint32_t h = map8 ? map8[blockIdx.x >> 3] : 0u;
+    const Inst I = tab[h];
+    if (I.step0 != 0) return;
+    double *part = I.partial;   // slot 0
+    if (I.mode == MODE_MARCH) {
+        const ItemRange ir = item_range(I, I.nct, I.nseg);
+        const uint32_t PC = I.P * I.C;
+        for (uint32_t it = ir.first; it < ir.count; it += ir.stride) {
+            const uint32_t sg = it / ir.nu;
+            const uint32_t ct = ir.ub + (it - sg * ir.nu);
+            const uint32_t e = ct * BLOCK + threadIdx.x;
+            Dots<S> acc;
+            if (e < PC) {
+                const uint32_t p = fdiv(e, I.fC), c = e - p * I.C;
+                const uint32_t m0 = sg * I.S, m1 = min(m0 + I.S, I.Lm);
+                for (uint32_t m = m0; m < m1; ++m) {
+                    const uint32_t i = p + I.P * m;
+                    const auto v = start_chunk<S>(I, i, c);
+                    G::st(I.buf0, i * I.C + c, v);
+                    acc.norm_only(v);
+                }
+            }
+            block_reduce_store<Dots<S>::DD>(acc.s0, acc.c0, acc.s1, acc.c1, part + (size_t)(sg * I.nct + ct) * 4);
+        }
+    } else {
+        const ItemRange ir = item_range(I, I.tiles, 1);
+        for (uint32_t it = ir.first; it < ir.count; it += ir.stride) {
+            const uint32_t t = ir.ub + it;
+            Dots<S> acc;
+            for (int u = 0; u < I.tpt; ++u) {
+                const uint32_t e = t * (uint32_t)(BLOCK * I.tpt) + (uint32_t)(u * BLOCK) + threadIdx.x;
+                if (e < I.nel) {
+                    const uint32_t i = fdiv(e, I.fC), c = e - i * I.C;
+                    const auto v = start_chunk<S>(I, i, c);
+                    G::st(I.buf0, e, v);
+                    acc.norm_only(v);
+                }
+            }
+            block_reduce_store<Dots<S>::DD>(acc.s0, acc.c0, acc.s1, acc.c1, part + (size_t)t * 4);
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
-// the fused recursion step
+// operator application on one chunk, in the oracle's slot order
+// (diagonal, -x, +x, -y, +y[, -z, +z])
 // ---------------------------------------------------------------------------
-template <typename S, int OPK>
-__device__ __forceinline__ void step_elem(const Inst *__restrict__ I, uint32_t e, const S *__restrict__ cur,
-                                          S *__restrict__ nxt, bool first, Dots<S> &acc)
+// Real hopping: a = d*v + h*(v_-x) + h*(v_+x) + ...
+template <typename S, int NS>
+__device__ __forceinline__ typename V16<S>::T apply_real(bool hd, S d, S h, typename V16<S>::T v,
+                                                         const typename V16<S>::T (&nb)[NS])
 {
-    typedef typename V16<S>::T T;
+    typedef Arith<S> A;
+    typename V16<S>::T a;
+    if (hd) {
+        a = d * v;
+        a = A::mac(a, h, nb[0]);
+    } else {
+        a = h * nb[0];
+    }
+#pragma unroll
+    for (int s = 1; s < NS; ++s) a = A::mac(a, h, nb[s]);
+    return a;
+}
+// Complex hopping: slot s has coefficient (hr[s], hi[s]).
+template <typename S, int NS>
+__device__ __forceinline__ typename V16<S>::T apply_cplx(bool hd, S d, typename V16<S>::T v,
+                                                         const typename V16<S>::T (&nb)[NS], const S (&hr)[NS],
+                                                         const S (&hi)[NS])
+{
     typedef Arith<S> A;
     constexpr int W = V16<S>::W;
-    const uint32_t i = fdiv(e, I->fC);
-    const uint32_t c = e - i * I->C;
-    const uint32_t Rs = I->Rs;
-    const size_t cw = (size_t)c * W;
-    const size_t off = (size_t)i * Rs + cw;
-    const T v = ld16(cur + off);
+    typename V16<S>::T out;
+#pragma unroll
+    for (int l = 0; l < W / 2; ++l) {
+        S ar, ai;
+        if (hd) {
+            ar = d * v[2 * l];
+            ai = d * v[2 * l + 1];
+            A::cmac(ar, ai, hr[0], hi[0], nb[0][2 * l], nb[0][2 * l + 1]);
+        } else {
+            A::cmul(ar, ai, hr[0], hi[0], nb[0][2 * l], nb[0][2 * l + 1]);
+        }
+#pragma unroll
+        for (int s = 1; s < NS; ++s) A::cmac(ar, ai, hr[s], hi[s], nb[s][2 * l], nb[s][2 * l + 1]);
+        out[2 * l] = ar;
+        out[2 * l + 1] = ai;
+    }
+    return out;
+}
+
+// ---------------------------------------------------------------------------
+// the fused recursion step, march form (lattices)
+// ---------------------------------------------------------------------------
+template <typename S, int OPK, bool WIDE>
+__global__ __launch_bounds__(BLOCK) void k_step_march(const Inst *__restrict__ tab,
+                                                      const uint32_t *__restrict__ map8, int32_t k)
+{
+    typedef typename V16<S>::T T;
+    typedef Mem<S, WIDE> G;
+    typedef typename Mem<S, WIDE>::S2 S2;
+    constexpr bool D3 = (OPK == OP_REAL3 || OPK == OP_SPIN3);
+    constexpr bool SPIN = (OPK == OP_SPIN2 || OPK == OP_SPIN3);
+    constexpr int DIM = D3 ? 3 : 2;
+    constexpr int NS = 2 * DIM;
+    const uint32_t h = map8 ? map8[blockIdx.x >> 3] : 0u;
+    const Inst I = tab[h];
+    const int32_t n = I.step0 + k;
+    if (n < 0 || n >= I.K) return;
+    const void *cur = (n & 1) ? I.buf1 : I.buf0;
+    void *nxt = (n & 1) ? I.buf0 : I.buf1;
+    const bool first = (n == 0);
+    const bool hd = I.has_diag;
+    S hop = 0;
+    if (!SPIN) hop = G::lds(I.hop, 0);
+    double *part = I.partial + (size_t)((n + 1) % I.pslots) * I.tiles * 4;
+    const uint32_t C = I.C, P = I.P, Lx = I.Lx, Ly = I.Ly, Lm = I.Lm;
+    const uint32_t PC = P * C;
+    const ItemRange ir = item_range(I, I.nct, I.nseg);
+    for (uint32_t it = ir.first; it < ir.count; it += ir.stride) {
+        const uint32_t sg = it / ir.nu;
+        const uint32_t ct = ir.ub + (it - sg * ir.nu);
+        const uint32_t e = ct * BLOCK + threadIdx.x;
+        Dots<S> acc;
+        if (e < PC) {
+            const uint32_t p = fdiv(e, I.fC), c = e - p * C;
+            uint32_t x = p, y = 0;
+            if (D3) {
+                y = fdiv(p, I.fLx);
+                x = p - y * Lx;
+            }
+            const uint32_t pxm = (x == 0) ? p + (Lx - 1) : p - 1;
+            const uint32_t pxp = (x == Lx - 1) ? p - (Lx - 1) : p + 1;
+            uint32_t pym = 0, pyp = 0;
+            if (D3) {
+                pym = (y == 0) ? p + (Ly - 1) * Lx : p - Lx;
+                pyp = (y == Ly - 1) ? p - (Ly - 1) * Lx : p + Lx;
+            }
+            const uint32_t m0 = sg * I.S, m1 = min(m0 + I.S, Lm);
+            const uint32_t mb = (m0 == 0) ? Lm - 1 : m0 - 1;
+            T vm = G::ld(cur, (p + P * mb) * C + c);   // plane m-1
+            T v0 = G::ld(cur, (p + P * m0) * C + c);   // plane m
+            S2 bmarch = {0, 0};                        // march-axis bond from plane m-1 to m
+            if (SPIN) bmarch = G::ldc(I.bond, (p + P * mb) * DIM + (DIM - 1));
+            for (uint32_t m = m0; m < m1; ++m) {
+                const uint32_t mn = (m + 1 == Lm) ? 0 : m + 1;
+                const uint32_t i = p + P * m;
+                const uint32_t ch = i * C + c;
+                const T vp = G::ld(cur, (p + P * mn) * C + c);
+                T nb[NS];
+                nb[0] = G::ld(cur, (pxm + P * m) * C + c);
+                nb[1] = G::ld(cur, (pxp + P * m) * C + c);
+                if (D3) {
+                    nb[2] = G::ld(cur, (pym + P * m) * C + c);
+                    nb[3] = G::ld(cur, (pyp + P * m) * C + c);
+                }
+                nb[NS - 2] = vm;
+                nb[NS - 1] = vp;
+                T prev;
+                if (!first) prev = G::ld_nt(nxt, ch);
+                const S d = hd ? G::lds(I.diag, i) : (S)0;
+                T out;
+                if (!SPIN) {
+                    out = apply_real<S, NS>(hd, d, hop, v0, nb);
+                } else {
+                    S hr[NS], hi[NS];
+                    const S2 bxm = G::ldc(I.bond, (pxm + P * m) * DIM + 0);
+                    const S2 bxp = G::ldc(I.bond, i * DIM + 0);
+                    hr[0] = bxm[0]; hi[0] = -bxm[1];
+                    hr[1] = bxp[0]; hi[1] = bxp[1];
+                    if (D3) {
+                        const S2 bym = G::ldc(I.bond, (pym + P * m) * DIM + 1);
+                        const S2 byp = G::ldc(I.bond, i * DIM + 1);
+                        hr[2] = bym[0]; hi[2] = -bym[1];
+                        hr[3] = byp[0]; hi[3] = byp[1];
+                    }
+                    const S2 bnext = G::ldc(I.bond, i * DIM + (DIM - 1));
+                    hr[NS - 2] = bmarch[0]; hi[NS - 2] = -bmarch[1];
+                    hr[NS - 1] = bnext[0]; hi[NS - 1] = bnext[1];
+                    out = apply_cplx<S, NS>(hd, d, v0, nb, hr, hi);
+                    bmarch = bnext;
+                }
+                if (!first) out = (S)2 * out - prev;
+                G::st_nt(nxt, ch, out);
+                acc.add(out, v0);
+                vm = v0;
+                v0 = vp;
+            }
+        }
+        block_reduce_store<Dots<S>::DD>(acc.s0, acc.c0, acc.s1, acc.c1, part + (size_t)(sg * I.nct + ct) * 4);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// the fused recursion step, flat form (CSR; lattices on request)
+// ---------------------------------------------------------------------------
+template <typename S, int OPK, bool WIDE>
+__device__ __forceinline__ void flat_elem(const Inst &I, uint32_t e, const void *cur, void *nxt, bool first, S hop,
+                                          Dots<S> &acc)
+{
+    typedef typename V16<S>::T T;
+    typedef Mem<S, WIDE> G;
+    typedef typename Mem<S, WIDE>::S2 S2;
+    typedef Arith<S> A;
+    constexpr int W = V16<S>::W;
+    const uint32_t C = I.C;
+    const uint32_t i = fdiv(e, I.fC);
+    const uint32_t c = e - i * C;
+    const T v = G::ld(cur, e);
     T out;
     if constexpr (OPK <= OP_SPIN3) {
         constexpr bool D3 = (OPK == OP_REAL3 || OPK == OP_SPIN3);
         constexpr bool SPIN = (OPK == OP_SPIN2 || OPK == OP_SPIN3);
-        const uint32_t Lx = I->Lx, Ly = I->Ly;
-        const uint32_t yq = fdiv(i, I->fLx);
+        constexpr int DIM = D3 ? 3 : 2;
+        constexpr int NS = 2 * DIM;
+        const uint32_t Lx = I.Lx, Ly = I.Ly;
+        const uint32_t yq = fdiv(i, I.fLx);
         const uint32_t x = i - yq * Lx;
         uint32_t y = yq, z = 0;
         if (D3) {
-            z = fdiv(yq, I->fLy);
+            z = fdiv(yq, I.fLy);
             y = yq - z * Ly;
         }
-        const uint32_t xm = (x == 0) ? i + (Lx - 1) : i - 1;
-        const uint32_t xp = (x == Lx - 1) ? i - (Lx - 1) : i + 1;
-        const uint32_t ym = (y == 0) ? i + (Ly - 1) * Lx : i - Lx;
-        const uint32_t yp = (y == Ly - 1) ? i - (Ly - 1) * Lx : i + Lx;
-        uint32_t zm = 0, zp = 0;
+        uint32_t nbi[NS];
+        nbi[0] = (x == 0) ? i + (Lx - 1) : i - 1;
+        nbi[1] = (x == Lx - 1) ? i - (Lx - 1) : i + 1;
+        nbi[2] = (y == 0) ? i + (Ly - 1) * Lx : i - Lx;
+        nbi[3] = (y == Ly - 1) ? i - (Ly - 1) * Lx : i + Lx;
         if (D3) {
-            const uint32_t Pz = Lx * Ly, Lz = I->Lz;
-            zm = (z == 0) ? i + (Lz - 1) * Pz : i - Pz;
-            zp = (z == Lz - 1) ? i - (Lz - 1) * Pz : i + Pz;
+            const uint32_t Pz = Lx * Ly, Lz = I.Lz;
+            nbi[4] = (z == 0) ? i + (Lz - 1) * Pz : i - Pz;
+            nbi[5] = (z == Lz - 1) ? i - (Lz - 1) * Pz : i + Pz;
         }
-        const T vxm = ld16(cur + (size_t)xm * Rs + cw);
-        const T vxp = ld16(cur + (size_t)xp * Rs + cw);
-        const T vym = ld16(cur + (size_t)ym * Rs + cw);
-        const T vyp = ld16(cur + (size_t)yp * Rs + cw);
-        T vzm, vzp;
-        if (D3) {
-            vzm = ld16(cur + (size_t)zm * Rs + cw);
-            vzp = ld16(cur + (size_t)zp * Rs + cw);
-        }
-        if constexpr (!SPIN) {
-            const S hh = *(const S *)I->hop;
-            T a;
-            if (I->has_diag) {
-                const S d = ((const S *)I->diag)[i];
-                a = d * v;
-                a = A::mac(a, hh, vxm);
-            } else {
-                a = hh * vxm;
-            }
-            a = A::mac(a, hh, vxp);
-            a = A::mac(a, hh, vym);
-            a = A::mac(a, hh, vyp);
-            if (D3) {
-                a = A::mac(a, hh, vzm);
-                a = A::mac(a, hh, vzp);
-            }
-            out = a;
-        } else {
-            constexpr int DIM = D3 ? 3 : 2;
-            const S *B = (const S *)I->bond;
-            // slot order -x, +x, -y, +y[, -z, +z]; H~_{i,i-e} = conj(H~_{i-e,i})
-            const S bxm_r = B[((size_t)xm * DIM + 0) * 2], bxm_i = -B[((size_t)xm * DIM + 0) * 2 + 1];
-            const S bxp_r = B[((size_t)i * DIM + 0) * 2], bxp_i = B[((size_t)i * DIM + 0) * 2 + 1];
-            const S bym_r = B[((size_t)ym * DIM + 1) * 2], bym_i = -B[((size_t)ym * DIM + 1) * 2 + 1];
-            const S byp_r = B[((size_t)i * DIM + 1) * 2], byp_i = B[((size_t)i * DIM + 1) * 2 + 1];
-            S bzm_r = 0, bzm_i = 0, bzp_r = 0, bzp_i = 0;
-            if (D3) {
-                bzm_r = B[((size_t)zm * DIM + 2) * 2];
-                bzm_i = -B[((size_t)zm * DIM + 2) * 2 + 1];
-                bzp_r = B[((size_t)i * DIM + 2) * 2];
-                bzp_i = B[((size_t)i * DIM + 2) * 2 + 1];
-            }
-            const bool hd = I->has_diag;
-            const S d = hd ? ((const S *)I->diag)[i] : (S)0;
+        T nb[NS];
 #pragma unroll
-            for (int l = 0; l < W / 2; ++l) {
-                S ar, ai;
-                if (hd) {
-                    ar = d * v[2 * l];
-                    ai = d * v[2 * l + 1];
-                    A::cmac(ar, ai, bxm_r, bxm_i, vxm[2 * l], vxm[2 * l + 1]);
-                } else {
-                    A::cmul(ar, ai, bxm_r, bxm_i, vxm[2 * l], vxm[2 * l + 1]);
-                }
-                A::cmac(ar, ai, bxp_r, bxp_i, vxp[2 * l], vxp[2 * l + 1]);
-                A::cmac(ar, ai, bym_r, bym_i, vym[2 * l], vym[2 * l + 1]);
-                A::cmac(ar, ai, byp_r, byp_i, vyp[2 * l], vyp[2 * l + 1]);
-                if (D3) {
-                    A::cmac(ar, ai, bzm_r, bzm_i, vzm[2 * l], vzm[2 * l + 1]);
-                    A::cmac(ar, ai, bzp_r, bzp_i, vzp[2 * l], vzp[2 * l + 1]);
-                }
-                out[2 * l] = ar;
-                out[2 * l + 1] = ai;
+        for (int s = 0; s < NS; ++s) nb[s] = G::ld(cur, nbi[s] * C + c);
+        const bool hd = I.has_diag;
+        const S d = hd ? G::lds(I.diag, i) : (S)0;
+        if (!SPIN) {
+            out = apply_real<S, NS>(hd, d, hop, v, nb);
+        } else {
+            S hr[NS], hi[NS];
+#pragma unroll
+            for (int ax = 0; ax < DIM; ++ax) {
+                const S2 bm = G::ldc(I.bond, nbi[2 * ax] * DIM + ax);
+                const S2 bp = G::ldc(I.bond, i * DIM + ax);
+                hr[2 * ax] = bm[0]; hi[2 * ax] = -bm[1];
+                hr[2 * ax + 1] = bp[0]; hi[2 * ax + 1] = bp[1];
             }
+            out = apply_cplx<S, NS>(hd, d, v, nb, hr, hi);
         }
     } else {
         // CSR: the diagonal d_i first, then the off-diagonal entries in stored order
-        const int64_t kb = I->row_ptr[i], ke = I->row_ptr[i + 1];
-        const S d = ((const S *)I->diag)[i];
-        if constexpr (OPK == OP_CSR_R) {
-            T a = d * v;
-            const S *val = (const S *)I->val;
-            for (int64_t k = kb; k < ke; ++k) {
-                const uint32_t jj = (uint32_t)I->col[k];
-                if (jj == i) continue;
-                a = A::mac(a, val[k], ld16(cur + (size_t)jj * Rs + cw));
-            }
-            out = a;
-        } else {
-            T a;
+        const int64_t kb = I.row_ptr[i], ke = I.row_ptr[i + 1];
+        const S d = G::lds(I.diag, i);
+        T a;
 #pragma unroll
-            for (int l = 0; l < W; ++l) a[l] = d * v[l];
-            const S *val = (const S *)I->val;
-            for (int64_t k = kb; k < ke; ++k) {
-                const uint32_t jj = (uint32_t)I->col[k];
-                if (jj == i) continue;
-                const S hr = val[2 * k], hi = val[2 * k + 1];
-                const T vj = ld16(cur + (size_t)jj * Rs + cw);
+        for (int l = 0; l < W; ++l) a[l] = d * v[l];
+        for (int64_t kk = kb; kk < ke; ++kk) {
+            const uint32_t jj = (uint32_t)I.col[kk];
+            if (jj == i) continue;
+            const T vj = G::ld(cur, jj * C + c);
+            if constexpr (OPK == OP_CSR_R) {
+                a = A::mac(a, ((const S *)I.val)[kk], vj);
+            } else {
+                const S hr = ((const S *)I.val)[2 * kk], hi = ((const S *)I.val)[2 * kk + 1];
 #pragma unroll
                 for (int l = 0; l < W / 2; ++l) {
                     S ar = a[2 * l], ai = a[2 * l + 1];
@@ -404,47 +614,45 @@ __device__ __forceinline__ void step_elem(const Inst *__restrict__ I, uint32_t e
                     a[2 * l + 1] = ai;
                 }
             }
-            out = a;
         }
+        out = a;
     }
     if (!first) {
-        const T p = ld16_stream(nxt + off);
+        const T p = G::ld_nt(nxt, e);
         out = (S)2 * out - p;
     }
-    st16_stream(nxt + off, out);
+    G::st_nt(nxt, e, out);
     acc.add(out, v);
 }
 
-template <typename S, int OPK, int TPT>
-__global__ __launch_bounds__(BLOCK) void k_step(const Inst *__restrict__ tab, const uint32_t *__restrict__ map8,
-                                                int32_t k)
+template <typename S, int OPK, bool WIDE>
+__global__ __launch_bounds__(BLOCK) void k_step_flat(const Inst *__restrict__ tab, const uint32_t *__restrict__ map8,
+                                                     int32_t k)
 {
     const uint32_t h = map8 ? map8[blockIdx.x >> 3] : 0u;
-    const Inst *I = tab + h;
-    const int32_t n = I->step0 + k;
-    if (n < 0 || n >= I->K) return;
-    const uint32_t bl = blockIdx.x - I->block0;
-    const uint32_t x8 = bl & 7u, j = bl >> 3, q = I->nb >> 3;
-    const uint32_t tiles = I->tiles;
-    const uint32_t tb = (uint32_t)(((uint64_t)tiles * x8) >> 3);
-    const uint32_t te = (uint32_t)(((uint64_t)tiles * (x8 + 1)) >> 3);
-    const S *cur = (const S *)((n & 1) ? I->buf1 : I->buf0);
-    S *nxt = (S *)((n & 1) ? I->buf0 : I->buf1);
+    const Inst I = tab[h];
+    const int32_t n = I.step0 + k;
+    if (n < 0 || n >= I.K) return;
+    const void *cur = (n & 1) ? I.buf1 : I.buf0;
+    void *nxt = (n & 1) ? I.buf0 : I.buf1;
     const bool first = (n == 0);
-    double *part = I->partial + (size_t)((n + 1) % I->pslots) * tiles * 4;
-    for (uint32_t t = tb + j; t < te; t += q) {
+    S hop = 0;
+    if (OPK == OP_REAL2 || OPK == OP_REAL3) hop = Mem<S, WIDE>::lds(I.hop, 0);
+    double *part = I.partial + (size_t)((n + 1) % I.pslots) * I.tiles * 4;
+    const ItemRange ir = item_range(I, I.tiles, 1);
+    for (uint32_t it = ir.first; it < ir.count; it += ir.stride) {
+        const uint32_t t = ir.ub + it;
         Dots<S> acc;
-#pragma unroll
-        for (int u = 0; u < TPT; ++u) {
-            const uint32_t e = t * (uint32_t)(BLOCK * TPT) + (uint32_t)(u * BLOCK) + threadIdx.x;
-            if (e < I->nel) step_elem<S, OPK>(I, e, cur, nxt, first, acc);
+        for (int u = 0; u < I.tpt; ++u) {
+            const uint32_t e = t * (uint32_t)(BLOCK * I.tpt) + (uint32_t)(u * BLOCK) + threadIdx.x;
+            if (e < I.nel) flat_elem<S, OPK, WIDE>(I, e, cur, nxt, first, hop, acc);
         }
         block_reduce_store<Dots<S>::DD>(acc.s0, acc.c0, acc.s1, acc.c1, part + (size_t)t * 4);
     }
 }
 
 // ---------------------------------------------------------------------------
-// reduction of the per-tile partials and the moments
+// reduction of the per-item partials and the moments
 // ---------------------------------------------------------------------------
 // Block (x, h): dots index idx = step0 + 1 + klo + x of instance h, for x < nk.
 __global__ __launch_bounds__(BLOCK) void k_reduce(const Inst *__restrict__ tab, int32_t klo, int32_t nk)

@@ -16,8 +16,10 @@ using namespace kpm;
 namespace {
 
 constexpr int PSLOTS_MAX = 64;          // ring slots of per-tile partials between reductions
-int g_tpt = 4;                          // chunks per thread per tile
+int g_tpt = 4;                          // flat kernels: chunks per thread per tile
 int g_max_blocks = 2048;                // blocks per instance per launch (multiple of 8)
+int g_march = 1;                        // lattices use the march kernels
+int g_march_items = 2048;               // target work items per instance when choosing march segments
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 inline hipStream_t S(void *s) { return (hipStream_t)s; }
@@ -294,27 +296,38 @@ __global__ __launch_bounds__(256) void k_export_start(int vec, int cplx, uint64_
 typedef void (*step_fn)(const Inst *, const uint32_t *, int32_t);
 typedef void (*init_fn)(const Inst *, const uint32_t *);
 
-template <typename S, int TPT>
-step_fn step_for(int opk)
+// Kernel class of a solve: one launch covers instances of one class.
+inline int kernel_key(int opk, int mode, int wide) { return (opk * 2 + mode) * 2 + wide; }
+
+template <typename S, bool WIDE>
+step_fn step_for(int opk, int mode)
 {
+    if (mode == MODE_MARCH) {
+        switch (opk) {
+        case OP_REAL2: return k_step_march<S, OP_REAL2, WIDE>;
+        case OP_REAL3: return k_step_march<S, OP_REAL3, WIDE>;
+        case OP_SPIN2: return k_step_march<S, OP_SPIN2, WIDE>;
+        default: return k_step_march<S, OP_SPIN3, WIDE>;
+        }
+    }
     switch (opk) {
-    case OP_REAL2: return k_step<S, OP_REAL2, TPT>;
-    case OP_REAL3: return k_step<S, OP_REAL3, TPT>;
-    case OP_SPIN2: return k_step<S, OP_SPIN2, TPT>;
-    case OP_SPIN3: return k_step<S, OP_SPIN3, TPT>;
-    case OP_CSR_R: return k_step<S, OP_CSR_R, TPT>;
-    default: return k_step<S, OP_CSR_C, TPT>;
+    case OP_REAL2: return k_step_flat<S, OP_REAL2, WIDE>;
+    case OP_REAL3: return k_step_flat<S, OP_REAL3, WIDE>;
+    case OP_SPIN2: return k_step_flat<S, OP_SPIN2, WIDE>;
+    case OP_SPIN3: return k_step_flat<S, OP_SPIN3, WIDE>;
+    case OP_CSR_R: return k_step_flat<S, OP_CSR_R, WIDE>;
+    default: return k_step_flat<S, OP_CSR_C, WIDE>;
     }
 }
-step_fn get_step(int prec, int opk, int tpt)
+step_fn get_step(int prec, int opk, int mode, int wide)
 {
-    if (prec == KPM_F64) return tpt == 1 ? step_for<double, 1>(opk) : tpt == 2 ? step_for<double, 2>(opk) : step_for<double, 4>(opk);
-    return tpt == 1 ? step_for<float, 1>(opk) : tpt == 2 ? step_for<float, 2>(opk) : step_for<float, 4>(opk);
+    if (prec == KPM_F64) return wide ? step_for<double, true>(opk, mode) : step_for<double, false>(opk, mode);
+    return wide ? step_for<float, true>(opk, mode) : step_for<float, false>(opk, mode);
 }
-init_fn get_init(int prec, int tpt)
+init_fn get_init(int prec, int wide)
 {
-    if (prec == KPM_F64) return tpt == 1 ? k_init<double, 1> : tpt == 2 ? k_init<double, 2> : k_init<double, 4>;
-    return tpt == 1 ? k_init<float, 1> : tpt == 2 ? k_init<float, 2> : k_init<float, 4>;
+    if (prec == KPM_F64) return wide ? k_init<double, true> : k_init<double, false>;
+    return wide ? k_init<float, true> : k_init<float, false>;
 }
 
 }  // namespace
@@ -338,6 +351,7 @@ struct kpm_ham {
 struct kpm_solve {
     kpm_ham *h;
     Inst inst;
+    int wide;
     char *ws;
     Inst *tab_dev;
     int32_t next;      // next recursion step n to run
@@ -349,9 +363,10 @@ namespace {
 
 // Geometry of one solve: everything but device pointers.
 struct Plan {
-    int cplx;
+    int cplx, mode, wide, xcd;
     uint32_t W, Rs, C, nel, tiles, nb;
-    int32_t K, P, tpt;
+    uint32_t P, Lm, S, nct, nseg;
+    int32_t K, P_slots, tpt;
     size_t esz;
     size_t part_bytes, dots_bytes, buf_bytes;
 };
@@ -359,6 +374,7 @@ struct Plan {
 bool make_plan(const kpm_ham *h, int32_t M, int32_t R, int32_t vec, Plan &p)
 {
     if (!h || M < 1 || R < 1 || vec < 0 || vec > 2) return false;
+    std::memset(&p, 0, sizeof(p));
     p.esz = h->prec == KPM_F64 ? 8 : 4;
     p.W = (uint32_t)(16 / p.esz);
     p.cplx = (h->cplx_op || vec == KPM_VEC_PHASE) ? 1 : 0;
@@ -371,13 +387,32 @@ bool make_plan(const kpm_ham *h, int32_t M, int32_t R, int32_t vec, Plan &p)
     p.C = (uint32_t)C;
     p.nel = (uint32_t)nel;
     p.tpt = g_tpt;
-    const uint64_t per_tile = (uint64_t)BLOCK * p.tpt;
-    p.tiles = (uint32_t)((nel + per_tile - 1) / per_tile);
-    uint32_t nb = (p.tiles + 7) / 8 * 8;
+    // byte offsets beyond 32 bits need the 64-bit addressing variant
+    const uint64_t bond_bytes = (uint64_t)h->N * (h->dim ? h->dim : 1) * 2 * p.esz;
+    p.wide = (nel * 16 >= (1ull << 32) || bond_bytes >= (1ull << 32)) ? 1 : 0;
+    if (h->dim && g_march) {
+        p.mode = MODE_MARCH;
+        p.P = (uint32_t)(h->dim == 3 ? h->L[0] * h->L[1] : h->L[0]);
+        p.Lm = (uint32_t)(h->dim == 3 ? h->L[2] : h->L[1]);
+        const uint64_t PC = (uint64_t)p.P * p.C;
+        p.nct = (uint32_t)((PC + BLOCK - 1) / BLOCK);
+        uint32_t nseg = (uint32_t)((g_march_items + p.nct - 1) / p.nct);
+        nseg = std::max<uint32_t>(1, std::min<uint32_t>(nseg, std::max<uint32_t>(1, p.Lm / 8)));
+        p.S = (p.Lm + nseg - 1) / nseg;
+        p.nseg = (p.Lm + p.S - 1) / p.S;
+        p.tiles = p.nct * p.nseg;
+        p.xcd = p.nct >= XCD_MIN_ITEMS ? 1 : 0;
+    } else {
+        p.mode = MODE_FLAT;
+        const uint64_t per_tile = (uint64_t)BLOCK * p.tpt;
+        p.tiles = (uint32_t)((nel + per_tile - 1) / per_tile);
+        p.xcd = p.tiles >= XCD_MIN_ITEMS ? 1 : 0;
+    }
+    const uint32_t nb = (p.tiles + 7) / 8 * 8;
     p.nb = std::min<uint32_t>(nb, (uint32_t)g_max_blocks);
     p.K = M / 2;
-    p.P = std::min(p.K + 1, PSLOTS_MAX);
-    p.part_bytes = align256((size_t)p.P * p.tiles * 4 * sizeof(double));
+    p.P_slots = std::min(p.K + 1, PSLOTS_MAX);
+    p.part_bytes = align256((size_t)p.P_slots * p.tiles * 4 * sizeof(double));
     p.dots_bytes = align256((size_t)(p.K + 1) * 4 * sizeof(double));
     p.buf_bytes = align256((size_t)h->N * p.Rs * p.esz);
     return true;
@@ -405,13 +440,20 @@ void fill_inst(const kpm_ham *h, const Plan &p, int32_t M, int32_t R, int32_t ve
     I.nb = p.nb;
     I.block0 = 0;
     I.tpt = p.tpt;
+    I.mode = p.mode;
+    I.xcd = p.xcd;
+    I.P = p.P;
+    I.Lm = p.Lm;
+    I.S = p.S;
+    I.nct = p.nct;
+    I.nseg = p.nseg;
     I.cplx = p.cplx;
     I.M = M;
     I.K = p.K;
     I.R = R;
     I.vec = vec;
     I.step0 = 0;
-    I.pslots = p.P;
+    I.pslots = p.P_slots;
     I.seed = seed;
     I.instance = instance;
     I.norm = (vec == KPM_VEC_UNIT) ? (double)R : (double)h->N * (double)R;
@@ -428,15 +470,15 @@ void fill_inst(const kpm_ham *h, const Plan &p, int32_t M, int32_t R, int32_t ve
     I.mu = nullptr;
 }
 
-kpm_status launch_init(int prec, int tpt, const Inst *tab, const uint32_t *map8, uint32_t blocks, hipStream_t st)
+kpm_status launch_init(int prec, int wide, const Inst *tab, const uint32_t *map8, uint32_t blocks, hipStream_t st)
 {
-    hipLaunchKernelGGL(get_init(prec, tpt), dim3(blocks), dim3(BLOCK), 0, st, tab, map8);
+    hipLaunchKernelGGL(get_init(prec, wide), dim3(blocks), dim3(BLOCK), 0, st, tab, map8);
     return check_launch();
 }
-kpm_status launch_step(int prec, int opk, int tpt, const Inst *tab, const uint32_t *map8, uint32_t blocks, int32_t k,
-                       hipStream_t st)
+kpm_status launch_step(int prec, int opk, int mode, int wide, const Inst *tab, const uint32_t *map8, uint32_t blocks,
+                       int32_t k, hipStream_t st)
 {
-    hipLaunchKernelGGL(get_step(prec, opk, tpt), dim3(blocks), dim3(BLOCK), 0, st, tab, map8, k);
+    hipLaunchKernelGGL(get_step(prec, opk, mode, wide), dim3(blocks), dim3(BLOCK), 0, st, tab, map8, k);
     return check_launch();
 }
 kpm_status launch_reduce(const Inst *tab, int32_t count, int32_t klo, int32_t nk, hipStream_t st)
@@ -685,12 +727,13 @@ kpm_status kpm_solve_begin(kpm_ham *h, int32_t M, int32_t R, int32_t vec, uint64
     s->tab_dev = (Inst *)ws;
     fill_inst(h, p, M, R, vec, seed, instance, s->ws + align256(sizeof(Inst)), s->inst);
     kpm_status e = upload(s->tab_dev, &s->inst, sizeof(Inst), st);
-    if (e == KPM_OK) e = launch_init(h->prec, p.tpt, s->tab_dev, nullptr, p.nb, st);
+    s->wide = p.wide;
+    if (e == KPM_OK) e = launch_init(h->prec, p.wide, s->tab_dev, nullptr, p.nb, st);
     s->written = 1;
     s->reduced = 0;
     s->next = 0;
     if (e == KPM_OK && p.K >= 1) {
-        e = launch_step(h->prec, h->opk, p.tpt, s->tab_dev, nullptr, p.nb, 0, st);
+        e = launch_step(h->prec, h->opk, p.mode, p.wide, s->tab_dev, nullptr, p.nb, 0, st);
         s->next = 1;
         s->written = 2;
     }
@@ -721,7 +764,7 @@ kpm_status kpm_solve_advance(kpm_solve *s, int32_t max_steps, void *stream, int3
     for (int32_t c = 0; c < max_steps && s->next < I.K && e == KPM_OK; ++c) {
         if (s->written - s->reduced >= I.pslots) e = solve_reduce_pending(s, st);
         if (e != KPM_OK) break;
-        e = launch_step(s->h->prec, I.opk, I.tpt, s->tab_dev, nullptr, I.nb, s->next, st);
+        e = launch_step(s->h->prec, I.opk, I.mode, s->wide, s->tab_dev, nullptr, I.nb, s->next, st);
         s->next += 1;
         s->written += 1;
     }
@@ -765,7 +808,8 @@ namespace {
 struct BatchLayout {
     std::vector<Plan> plans;
     std::vector<int> group_of;       // instance -> group
-    std::vector<int> gopk;           // group -> operator kind
+    std::vector<int> gkey;           // group -> kernel class
+    std::vector<int> gopk, gmode, gwide;
     std::vector<std::vector<int>> members;
     std::vector<uint32_t> gblocks;   // blocks per group launch
     size_t tab_off, map_off, inst_off, total;
@@ -783,12 +827,16 @@ bool batch_layout(kpm_ham *const *h, int32_t count, const int32_t *M, const int3
     for (int i = 0; i < count; ++i) {
         if (!h[i] || h[i]->prec != L.prec) return false;
         if (!make_plan(h[i], M[i], R[i], vec, L.plans[i])) return false;
+        const int key = kernel_key(h[i]->opk, L.plans[i].mode, L.plans[i].wide);
         int g = -1;
-        for (size_t k = 0; k < L.gopk.size(); ++k)
-            if (L.gopk[k] == h[i]->opk) g = (int)k;
+        for (size_t k = 0; k < L.gkey.size(); ++k)
+            if (L.gkey[k] == key) g = (int)k;
         if (g < 0) {
-            g = (int)L.gopk.size();
+            g = (int)L.gkey.size();
+            L.gkey.push_back(key);
             L.gopk.push_back(h[i]->opk);
+            L.gmode.push_back(L.plans[i].mode);
+            L.gwide.push_back(L.plans[i].wide);
             L.members.emplace_back();
         }
         L.group_of[i] = g;
@@ -865,9 +913,8 @@ kpm_status kpm_moments_batched(kpm_ham *const *h, int32_t count, const int32_t *
     uint32_t *map_dev = (uint32_t *)(base + L.map_off);
     kpm_status e = upload(tab_dev, tab.data(), tab.size() * sizeof(Inst), st);
     if (e == KPM_OK && !map.empty()) e = upload(map_dev, map.data(), map.size() * 4, st);
-    const int tpt = L.plans[0].tpt;
     for (size_t g = 0; g < L.gopk.size() && e == KPM_OK; ++g)
-        e = launch_init(L.prec, tpt, tab_dev + gfirst[g], map_dev + L.map_goff[g], L.gblocks[g], st);
+        e = launch_init(L.prec, L.gwide[g], tab_dev + gfirst[g], map_dev + L.map_goff[g], L.gblocks[g], st);
     int32_t written = 1, reduced = 0;  // dots indices, in lockstep for every instance
     for (int32_t k = 0; k < Kmax && e == KPM_OK; ++k) {
         if (written - reduced >= PSLOTS_MAX) {
@@ -875,7 +922,8 @@ kpm_status kpm_moments_batched(kpm_ham *const *h, int32_t count, const int32_t *
             reduced = written;
         }
         for (size_t g = 0; g < L.gopk.size() && e == KPM_OK; ++g)
-            e = launch_step(L.prec, L.gopk[g], tpt, tab_dev + gfirst[g], map_dev + L.map_goff[g], L.gblocks[g], k, st);
+            e = launch_step(L.prec, L.gopk[g], L.gmode[g], L.gwide[g], tab_dev + gfirst[g], map_dev + L.map_goff[g],
+                            L.gblocks[g], k, st);
         written += 1;
     }
     if (e == KPM_OK) e = launch_reduce(tab_dev, count, reduced - 1, written - reduced, st);
@@ -904,22 +952,39 @@ kpm_status kpm_start_vectors(int32_t vec, int32_t complex_layout, uint64_t seed,
     return check_launch();
 }
 
-kpm_status kpm_set_launch(int32_t elems_per_thread, int32_t max_blocks)
+kpm_status kpm_set_launch(int32_t key, int32_t value)
 {
-    if (elems_per_thread != 0 && elems_per_thread != 1 && elems_per_thread != 2 && elems_per_thread != 4)
-        return KPM_ERR_INVALID_ARG;
-    if (max_blocks != 0 && (max_blocks < 8 || (max_blocks % 8) != 0)) return KPM_ERR_INVALID_ARG;
-    if (elems_per_thread) g_tpt = elems_per_thread;
-    if (max_blocks) g_max_blocks = max_blocks;
-    return KPM_OK;
+    switch (key) {
+    case KPM_LAUNCH_ELEMS_PER_THREAD:
+        if (value != 1 && value != 2 && value != 4) return KPM_ERR_INVALID_ARG;
+        g_tpt = value;
+        return KPM_OK;
+    case KPM_LAUNCH_MAX_BLOCKS:
+        if (value < 8 || (value % 8) != 0) return KPM_ERR_INVALID_ARG;
+        g_max_blocks = value;
+        return KPM_OK;
+    case KPM_LAUNCH_MARCH:
+        if (value != 0 && value != 1) return KPM_ERR_INVALID_ARG;
+        g_march = value;
+        return KPM_OK;
+    case KPM_LAUNCH_MARCH_ITEMS:
+        if (value < 1) return KPM_ERR_INVALID_ARG;
+        g_march_items = value;
+        return KPM_OK;
+    }
+    return KPM_ERR_INVALID_ARG;
 }
 
-kpm_status kpm_get_launch(int32_t *elems_per_thread, int32_t *max_blocks)
+kpm_status kpm_get_launch(int32_t key, int32_t *value)
 {
-    if (!elems_per_thread || !max_blocks) return KPM_ERR_INVALID_ARG;
-    *elems_per_thread = g_tpt;
-    *max_blocks = g_max_blocks;
-    return KPM_OK;
+    if (!value) return KPM_ERR_INVALID_ARG;
+    switch (key) {
+    case KPM_LAUNCH_ELEMS_PER_THREAD: *value = g_tpt; return KPM_OK;
+    case KPM_LAUNCH_MAX_BLOCKS: *value = g_max_blocks; return KPM_OK;
+    case KPM_LAUNCH_MARCH: *value = g_march; return KPM_OK;
+    case KPM_LAUNCH_MARCH_ITEMS: *value = g_march_items; return KPM_OK;
+    }
+    return KPM_ERR_INVALID_ARG;
 }
 
 // Host-side self-check of the division-by-constant helper (used by CPU tests).

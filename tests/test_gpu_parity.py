@@ -109,17 +109,17 @@ def test_launch_shape_does_not_change_fp64_result():
     op = wl.spin_cubic_lattice(9, seed=21)
     lo, hi = gu.oracle_bounds(op)
     a, b = oracle.scale_from_bounds(lo, hi, 0.01)
-    old = kpm.get_launch()
     outs = []
-    try:
-        for tpt, mb in [(4, 2048), (4, 8), (2, 64), (1, 2048)]:
-            kpm.set_launch(tpt, mb)
+    for kw in [dict(max_blocks=2048), dict(max_blocks=8), dict(march_items=1), dict(march_items=100000),
+               dict(march=0, elems_per_thread=4), dict(march=0, elems_per_thread=4, max_blocks=8),
+               dict(march=0, elems_per_thread=1)]:
+        with kpm.launch_settings(**kw):
             outs.append(gu.gpu_moments(op, a, b, kpm.F64, 60, 5, wl.VEC_PHASE, seed=3))
-    finally:
-        kpm.set_launch(*old)
-    assert np.array_equal(outs[0], outs[1])              # same tiles, different grid: bitwise
-    for o in outs[2:]:
-        assert np.abs(o - outs[0]).max() <= 1e-12 * np.abs(outs[0]).max()
+    assert np.array_equal(outs[0], outs[1])              # same work items, different grid: bitwise
+    assert np.array_equal(outs[4], outs[5])
+    ref = gu.oracle_moments(op, a, b, 60, 5, wl.VEC_PHASE, seed=3)
+    for o in outs:
+        gu.assert_fp64(o, ref, "launch shape")
 
 
 def test_chunked_solve_is_bitwise_equal():

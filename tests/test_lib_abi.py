@@ -71,8 +71,11 @@ def test_argument_validation_without_device(L):
     assert L.kpm_moments(None, 16, 4, 0, 1, 0, None, 0, None, None) != 0
     assert L.kpm_dos(None, 16, 1, 64, 1.0, 0.0, None, None, None) == 1
     assert L.kpm_start_vectors(5, 0, 0, 0, 10, 2, None, None) == 1
+    assert L.kpm_set_launch(0, 3) == 1          # elems per thread must be 1, 2 or 4
+    assert L.kpm_set_launch(1, 12) == 1         # block cap must be a multiple of 8
+    assert L.kpm_set_launch(2, 5) == 1
     assert L.kpm_set_launch(3, 0) == 1
-    assert L.kpm_set_launch(0, 12) == 1
+    assert L.kpm_set_launch(9, 1) == 1
     d = kpm.HamDesc()
     d.kind = 3
     d.L[0], d.L[1], d.L[2] = 4, 0, 4             # zero extent
@@ -88,13 +91,9 @@ def test_argument_validation_without_device(L):
 
 def test_launch_settings_roundtrip(L):
     old = kpm.get_launch()
-    try:
-        kpm.set_launch(2, 1024)
-        assert kpm.get_launch() == (2, 1024)
-        kpm.set_launch(0, 0)
-        assert kpm.get_launch() == (2, 1024)
-    finally:
-        kpm.set_launch(*old)
+    with kpm.launch_settings(elems_per_thread=2, max_blocks=1024, march=0, march_items=64):
+        assert kpm.get_launch() == {"elems_per_thread": 2, "max_blocks": 1024, "march": 0, "march_items": 64}
+    assert kpm.get_launch() == old
 
 
 def test_no_cpu_fallback_when_library_missing(monkeypatch):
