@@ -90,7 +90,7 @@ def cpu_baseline(lat, a, b, vec, seed):
     import oracle
     oracle.build()
     threads = oracle.max_threads()
-    Ms, Rs = 64, 4
+    Ms, Rs = (1024, 32) if lat.N <= 300000 else (64, 8)
     t0 = time.perf_counter()
     oracle.moments_lattice(lat.dim, lat.L[:lat.dim], lat.t, a, b, Ms, Rs, vec_kind=vec, seed=seed,
                            hop=lat.hop, onsite=lat.onsite, spinor=lat.spinor)
@@ -111,6 +111,8 @@ def main():
     ap.add_argument("--max-blocks", type=int, default=0)
     ap.add_argument("--march", type=int, default=-1, help="1: march kernels for lattices, 0: flat kernels")
     ap.add_argument("--march-items", type=int, default=0)
+    ap.add_argument("--xcd-split", type=int, default=-1, help="0 auto, 1 column tiles, 2 segments, 3 none")
+    ap.add_argument("--alternate", type=int, default=-1)
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain 1 GiB device copy three times (counter calibration under rocprofv3)")
     ap.add_argument("--pmc-summary", metavar="DIR",
@@ -144,7 +146,9 @@ def main():
         torch.cuda.synchronize()
         del x, y
     kpm.set_launch(elems_per_thread=args.tpt or None, max_blocks=args.max_blocks or None,
-                   march=None if args.march < 0 else args.march, march_items=args.march_items or None)
+                   march=None if args.march < 0 else args.march, march_items=args.march_items or None,
+                   xcd_split=None if args.xcd_split < 0 else args.xcd_split,
+                   alternate=None if args.alternate < 0 else args.alternate)
     dev = "cuda"
     stream = torch.cuda.current_stream()
 

@@ -197,6 +197,9 @@ kpm_status kpm_start_vectors(int32_t vec, int32_t complex_layout, uint64_t seed,
  *   KPM_LAUNCH_MARCH             1: lattices use the march kernels; 0: the flat kernels
  *   KPM_LAUNCH_MARCH_ITEMS       target work items per instance when the march axis is cut
  *                                into segments (fewer items -> longer segments)
+ *   KPM_LAUNCH_XCD_SPLIT         how an instance's work items are split over the 8 XCDs:
+ *                                0 automatic, 1 by column tiles, 2 by march segments, 3 none
+ *   KPM_LAUNCH_ALTERNATE         1: odd march segments walk downwards
  * The partial sums of the dot products are formed per work item, so the
  * moments do not depend on the grid (MAX_BLOCKS) nor on the batch an instance
  * runs in; the other keys change the work items and with them the order in
@@ -206,7 +209,9 @@ typedef enum {
     KPM_LAUNCH_ELEMS_PER_THREAD = 0,
     KPM_LAUNCH_MAX_BLOCKS = 1,
     KPM_LAUNCH_MARCH = 2,
-    KPM_LAUNCH_MARCH_ITEMS = 3
+    KPM_LAUNCH_MARCH_ITEMS = 3,
+    KPM_LAUNCH_XCD_SPLIT = 4,
+    KPM_LAUNCH_ALTERNATE = 5
 } kpm_launch_key;
 kpm_status kpm_set_launch(int32_t key, int32_t value);
 kpm_status kpm_get_launch(int32_t key, int32_t *value);

@@ -50,7 +50,8 @@ struct Inst {
     int32_t opk;
     int32_t has_diag;
     int32_t mode;
-    int32_t xcd;       // items split per XCD
+    int32_t xcd;       // items split per XCD (0 none, 1 by units, 2 by segments)
+    int32_t alt;       // march: odd segments walk downwards
     uint32_t Lx, Ly, Lz, N;
     FastDiv fLx, fLy, fC;
     uint32_t C;        // 16-byte chunks per site
@@ -247,30 +248,41 @@ __device__ __forceinline__ void block_reduce_store(double x0, double x1, double 
 // ---------------------------------------------------------------------------
 // mapping of an instance's blocks to its work items
 // ---------------------------------------------------------------------------
-// Items [0, count) of this instance handled by the block: first, stride, end,
-// and the offset that turns a local index into the item number.  With the XCD
-// split, XCD x handles the x-th eighth of the "unit" range (column tiles or
-// tiles) for every segment; `per` is the number of units.
+// Work items of this instance handled by the block.  An item is (unit, seg)
+// with unit a column tile (march) or tile (flat).  Local item index it ->
+// seg = sb + it / nu, unit = ub + it % nu, for it = first, first + stride, ...
+// below count.  XCD split (block b runs on XCD b mod 8):
+//   xcd == 2: XCD x owns segments [x*segs/8, (x+1)*segs/8) of every unit, so a
+//             whole plane stays in one L2;
+//   xcd == 1: XCD x owns units [x*units/8, (x+1)*units/8) of every segment;
+//   xcd == 0: no split.
 struct ItemRange {
-    uint32_t first, stride, count, ub, nu;   // local items [first, count) step stride; units [ub, ub+nu)
+    uint32_t first, stride, count, ub, nu, sb;
 };
 __device__ __forceinline__ ItemRange item_range(const Inst &I, uint32_t units, uint32_t segs)
 {
     const uint32_t bl = blockIdx.x - I.block0;
     ItemRange r;
+    r.ub = 0;
+    r.nu = units;
+    r.sb = 0;
+    uint32_t ns = segs;
     if (I.xcd) {
         const uint32_t x8 = bl & 7u;
-        r.ub = (uint32_t)(((uint64_t)units * x8) >> 3);
-        r.nu = (uint32_t)(((uint64_t)units * (x8 + 1)) >> 3) - r.ub;
+        if (I.xcd == 2) {
+            r.sb = (uint32_t)(((uint64_t)segs * x8) >> 3);
+            ns = (uint32_t)(((uint64_t)segs * (x8 + 1)) >> 3) - r.sb;
+        } else {
+            r.ub = (uint32_t)(((uint64_t)units * x8) >> 3);
+            r.nu = (uint32_t)(((uint64_t)units * (x8 + 1)) >> 3) - r.ub;
+        }
         r.first = bl >> 3;
         r.stride = I.nb >> 3;
     } else {
-        r.ub = 0;
-        r.nu = units;
         r.first = bl;
         r.stride = I.nb;
     }
-    r.count = r.nu * segs;
+    r.count = r.nu * ns;
     return r;
 }
 
@@ -348,8 +360,9 @@ __global__ __launch_bounds__(BLOCK) void k_init(const Inst *__restrict__ tab, co
         const ItemRange ir = item_range(I, I.nct, I.nseg);
         const uint32_t PC = I.P * I.C;
         for (uint32_t it = ir.first; it < ir.count; it += ir.stride) {
-            const uint32_t sg = it / ir.nu;
-            const uint32_t ct = ir.ub + (it - sg * ir.nu);
+            const uint32_t sl = it / ir.nu;
+            const uint32_t sg = ir.sb + sl;
+            const uint32_t ct = ir.ub + (it - sl * ir.nu);
             const uint32_t e = ct * BLOCK + threadIdx.x;
             Dots<S> acc;
             if (e < PC) {
@@ -460,8 +473,9 @@ __global__ __launch_bounds__(BLOCK) void k_step_march(const Inst *__restrict__ t
     const uint32_t PC = P * C;
     const ItemRange ir = item_range(I, I.nct, I.nseg);
     for (uint32_t it = ir.first; it < ir.count; it += ir.stride) {
-        const uint32_t sg = it / ir.nu;
-        const uint32_t ct = ir.ub + (it - sg * ir.nu);
+        const uint32_t sl = it / ir.nu;
+        const uint32_t sg = ir.sb + sl;
+        const uint32_t ct = ir.ub + (it - sl * ir.nu);
         const uint32_t e = ct * BLOCK + threadIdx.x;
         Dots<S> acc;
         if (e < PC) {
@@ -479,16 +493,24 @@ __global__ __launch_bounds__(BLOCK) void k_step_march(const Inst *__restrict__ t
                 pyp = (y == Ly - 1) ? p - (Ly - 1) * Lx : p + Lx;
             }
             const uint32_t m0 = sg * I.S, m1 = min(m0 + I.S, Lm);
-            const uint32_t mb = (m0 == 0) ? Lm - 1 : m0 - 1;
-            T vm = G::ld(cur, (p + P * mb) * C + c);   // plane m-1
-            T v0 = G::ld(cur, (p + P * m0) * C + c);   // plane m
-            S2 bmarch = {0, 0};                        // march-axis bond from plane m-1 to m
-            if (SPIN) bmarch = G::ldc(I.bond, (p + P * mb) * DIM + (DIM - 1));
-            for (uint32_t m = m0; m < m1; ++m) {
-                const uint32_t mn = (m + 1 == Lm) ? 0 : m + 1;
+            // Odd segments march downwards, so that two adjacent segments reach
+            // their common boundary planes at about the same time and the second
+            // read of a halo plane hits in L2.
+            const bool down = I.alt && (sg & 1u) != 0;
+            const uint32_t mfirst = down ? m1 - 1 : m0;
+            const uint32_t mbefore = down ? ((m1 == Lm) ? 0 : m1) : ((m0 == 0) ? Lm - 1 : m0 - 1);
+            // window: vb = plane behind (in march order), v0 = current plane
+            T vb = G::ld(cur, (p + P * mbefore) * C + c);
+            T v0 = G::ld(cur, (p + P * mfirst) * C + c);
+            // march-axis bond linking plane mbefore and mfirst (H~_{(m-1), m} stored at plane m-1)
+            S2 bb = {0, 0};
+            if (SPIN) bb = G::ldc(I.bond, (p + P * (down ? mfirst : mbefore)) * DIM + (DIM - 1));
+            for (uint32_t s_ = 0; s_ < m1 - m0; ++s_) {
+                const uint32_t m = down ? mfirst - s_ : mfirst + s_;
+                const uint32_t ma = down ? ((m == 0) ? Lm - 1 : m - 1) : ((m + 1 == Lm) ? 0 : m + 1);  // plane ahead
                 const uint32_t i = p + P * m;
                 const uint32_t ch = i * C + c;
-                const T vp = G::ld(cur, (p + P * mn) * C + c);
+                const T va = G::ld(cur, (p + P * ma) * C + c);
                 T nb[NS];
                 nb[0] = G::ld(cur, (pxm + P * m) * C + c);
                 nb[1] = G::ld(cur, (pxp + P * m) * C + c);
@@ -496,8 +518,9 @@ __global__ __launch_bounds__(BLOCK) void k_step_march(const Inst *__restrict__ t
                     nb[2] = G::ld(cur, (pym + P * m) * C + c);
                     nb[3] = G::ld(cur, (pyp + P * m) * C + c);
                 }
-                nb[NS - 2] = vm;
-                nb[NS - 1] = vp;
+                // slots -march, +march in the fixed order
+                nb[NS - 2] = down ? va : vb;
+                nb[NS - 1] = down ? vb : va;
                 T prev;
                 if (!first) prev = G::ld_nt(nxt, ch);
                 const S d = hd ? G::lds(I.diag, i) : (S)0;
@@ -516,17 +539,21 @@ __global__ __launch_bounds__(BLOCK) void k_step_march(const Inst *__restrict__ t
                         hr[2] = bym[0]; hi[2] = -bym[1];
                         hr[3] = byp[0]; hi[3] = byp[1];
                     }
-                    const S2 bnext = G::ldc(I.bond, i * DIM + (DIM - 1));
-                    hr[NS - 2] = bmarch[0]; hi[NS - 2] = -bmarch[1];
-                    hr[NS - 1] = bnext[0]; hi[NS - 1] = bnext[1];
+                    // the other march-axis bond: H~_{m, m+1} (up) lives at plane m,
+                    // H~_{m-1, m} (down) at plane m-1 = the plane ahead
+                    const S2 ba = G::ldc(I.bond, (p + P * (down ? ma : m)) * DIM + (DIM - 1));
+                    const S2 bminus = down ? ba : bb;   // H~_{m-1,m}: conjugated for slot -march
+                    const S2 bplus = down ? bb : ba;    // H~_{m,m+1}
+                    hr[NS - 2] = bminus[0]; hi[NS - 2] = -bminus[1];
+                    hr[NS - 1] = bplus[0]; hi[NS - 1] = bplus[1];
                     out = apply_cplx<S, NS>(hd, d, v0, nb, hr, hi);
-                    bmarch = bnext;
+                    bb = ba;
                 }
                 if (!first) out = (S)2 * out - prev;
                 G::st_nt(nxt, ch, out);
                 acc.add(out, v0);
-                vm = v0;
-                v0 = vp;
+                vb = v0;
+                v0 = va;
             }
         }
         block_reduce_store<Dots<S>::DD>(acc.s0, acc.c0, acc.s1, acc.c1, part + (size_t)(sg * I.nct + ct) * 4);

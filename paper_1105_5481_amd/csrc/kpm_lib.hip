@@ -19,7 +19,9 @@ constexpr int PSLOTS_MAX = 64;          // ring slots of per-tile partials betwe
 int g_tpt = 4;                          // flat kernels: chunks per thread per tile
 int g_max_blocks = 2048;                // blocks per instance per launch (multiple of 8)
 int g_march = 1;                        // lattices use the march kernels
-int g_march_items = 2048;               // target work items per instance when choosing march segments
+int g_march_items = 1024;               // target work items per instance when choosing march segments
+int g_xcd_split = 0;                    // 0 automatic, 1 by column tiles, 2 by segments, 3 none
+int g_alternate = 1;                    // march: odd segments walk downwards
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 inline hipStream_t S(void *s) { return (hipStream_t)s; }
@@ -363,7 +365,7 @@ namespace {
 
 // Geometry of one solve: everything but device pointers.
 struct Plan {
-    int cplx, mode, wide, xcd;
+    int cplx, mode, wide, xcd, alt;
     uint32_t W, Rs, C, nel, tiles, nb;
     uint32_t P, Lm, S, nct, nseg;
     int32_t K, P_slots, tpt;
@@ -401,7 +403,13 @@ bool make_plan(const kpm_ham *h, int32_t M, int32_t R, int32_t vec, Plan &p)
         p.S = (p.Lm + nseg - 1) / nseg;
         p.nseg = (p.Lm + p.S - 1) / p.S;
         p.tiles = p.nct * p.nseg;
-        p.xcd = p.nct >= XCD_MIN_ITEMS ? 1 : 0;
+        // split per XCD along the column tiles (measured best on the 64^3 and
+        // 2048^2 lattices), else along the march segments
+        p.xcd = p.nct >= XCD_MIN_ITEMS ? 1 : ((p.nseg >= 8 && p.tiles >= XCD_MIN_ITEMS) ? 2 : 0);
+        if (g_xcd_split == 1) p.xcd = p.nct >= XCD_MIN_ITEMS ? 1 : 0;
+        if (g_xcd_split == 2) p.xcd = p.nseg >= 8 ? 2 : 0;
+        if (g_xcd_split == 3) p.xcd = 0;
+        p.alt = g_alternate;
     } else {
         p.mode = MODE_FLAT;
         const uint64_t per_tile = (uint64_t)BLOCK * p.tpt;
@@ -442,6 +450,7 @@ void fill_inst(const kpm_ham *h, const Plan &p, int32_t M, int32_t R, int32_t ve
     I.tpt = p.tpt;
     I.mode = p.mode;
     I.xcd = p.xcd;
+    I.alt = p.alt;
     I.P = p.P;
     I.Lm = p.Lm;
     I.S = p.S;
@@ -971,6 +980,14 @@ kpm_status kpm_set_launch(int32_t key, int32_t value)
         if (value < 1) return KPM_ERR_INVALID_ARG;
         g_march_items = value;
         return KPM_OK;
+    case KPM_LAUNCH_XCD_SPLIT:
+        if (value < 0 || value > 3) return KPM_ERR_INVALID_ARG;
+        g_xcd_split = value;
+        return KPM_OK;
+    case KPM_LAUNCH_ALTERNATE:
+        if (value != 0 && value != 1) return KPM_ERR_INVALID_ARG;
+        g_alternate = value;
+        return KPM_OK;
     }
     return KPM_ERR_INVALID_ARG;
 }
@@ -983,6 +1000,8 @@ kpm_status kpm_get_launch(int32_t key, int32_t *value)
     case KPM_LAUNCH_MAX_BLOCKS: *value = g_max_blocks; return KPM_OK;
     case KPM_LAUNCH_MARCH: *value = g_march; return KPM_OK;
     case KPM_LAUNCH_MARCH_ITEMS: *value = g_march_items; return KPM_OK;
+    case KPM_LAUNCH_XCD_SPLIT: *value = g_xcd_split; return KPM_OK;
+    case KPM_LAUNCH_ALTERNATE: *value = g_alternate; return KPM_OK;
     }
     return KPM_ERR_INVALID_ARG;
 }

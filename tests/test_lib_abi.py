@@ -75,6 +75,8 @@ def test_argument_validation_without_device(L):
     assert L.kpm_set_launch(1, 12) == 1         # block cap must be a multiple of 8
     assert L.kpm_set_launch(2, 5) == 1
     assert L.kpm_set_launch(3, 0) == 1
+    assert L.kpm_set_launch(4, 4) == 1
+    assert L.kpm_set_launch(5, 2) == 1
     assert L.kpm_set_launch(9, 1) == 1
     d = kpm.HamDesc()
     d.kind = 3
@@ -91,8 +93,9 @@ def test_argument_validation_without_device(L):
 
 def test_launch_settings_roundtrip(L):
     old = kpm.get_launch()
-    with kpm.launch_settings(elems_per_thread=2, max_blocks=1024, march=0, march_items=64):
-        assert kpm.get_launch() == {"elems_per_thread": 2, "max_blocks": 1024, "march": 0, "march_items": 64}
+    with kpm.launch_settings(elems_per_thread=2, max_blocks=1024, march=0, march_items=64, xcd_split=3, alternate=0):
+        assert kpm.get_launch() == {"elems_per_thread": 2, "max_blocks": 1024, "march": 0, "march_items": 64,
+                                    "xcd_split": 3, "alternate": 0}
     assert kpm.get_launch() == old
 
 
