@@ -63,7 +63,11 @@ typedef enum { KPM_F64 = 0, KPM_F32 = 1 } kpm_prec;
  * device from Philox4x64-10 (Salmon et al., SC'11) with key (seed, 4) and
  * counter (i, floor(r/4), instance, 0), word r mod 4:
  *   RADEMACHER: xi_{r,i} = +1 or -1 (top bit of the word);   normalisation 1/(N R)
- *   PHASE:      xi_{r,i} = e^{i phi}, phi = 2 pi (word >> 11) 2^-53; normalisation 1/(N R)
+ *   PHASE:      xi_{r,i} = e^{i phi}, phi = 2 pi k / 2^30, k = word >> 34; e^{i phi} is the
+ *               ordered product over the set bits j of k (ascending) of w_j = e^{2 pi i 2^j/2^30},
+ *               w_j from the half-angle recurrence cos(t/2) = sqrt((1+cos t)/2),
+ *               sin(t/2) = sin t/(2 cos(t/2)) started at e^{i pi} and e^{i pi/2} (IEEE
+ *               operations only, so reproducible bit for bit);            normalisation 1/(N R)
  *   UNIT:       xi_r = e_j, j = (instance + r) mod N;        normalisation 1/R
  * With UNIT and R = N the moments are the exact traces Tr T_n(H~)/N (Eq. (DoStr)). */
 typedef enum { KPM_VEC_RADEMACHER = 0, KPM_VEC_PHASE = 1, KPM_VEC_UNIT = 2 } kpm_vec;
@@ -200,6 +204,8 @@ kpm_status kpm_start_vectors(int32_t vec, int32_t complex_layout, uint64_t seed,
  *   KPM_LAUNCH_XCD_SPLIT         how an instance's work items are split over the 8 XCDs:
  *                                0 automatic, 1 by column tiles, 2 by march segments, 3 none
  *   KPM_LAUNCH_ALTERNATE         1: odd march segments walk downwards
+ *   KPM_LAUNCH_SMALL             1: a solve whose two vector blocks fit in the LDS of one
+ *                                compute unit runs entirely in one workgroup (one launch)
  * The partial sums of the dot products are formed per work item, so the
  * moments do not depend on the grid (MAX_BLOCKS) nor on the batch an instance
  * runs in; the other keys change the work items and with them the order in
@@ -211,7 +217,8 @@ typedef enum {
     KPM_LAUNCH_MARCH = 2,
     KPM_LAUNCH_MARCH_ITEMS = 3,
     KPM_LAUNCH_XCD_SPLIT = 4,
-    KPM_LAUNCH_ALTERNATE = 5
+    KPM_LAUNCH_ALTERNATE = 5,
+    KPM_LAUNCH_SMALL = 6
 } kpm_launch_key;
 kpm_status kpm_set_launch(int32_t key, int32_t value);
 kpm_status kpm_get_launch(int32_t key, int32_t *value);

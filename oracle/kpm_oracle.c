@@ -22,7 +22,11 @@
  * SC'11, "Parallel random numbers: as easy as 1, 2, 3"):
  *   key = (seed, 4), counter = (i, floor(r/4), instance, 0), word = r mod 4
  *   Rademacher : xi = +1 if the top bit of the word is 0, else -1
- *   phase      : phi = 2 pi * (word >> 11) * 2^-53,  xi = cos(phi) + i sin(phi)
+ *   phase      : xi = e^{i phi}, phi = 2 pi k / 2^30 with k = word >> 34, evaluated exactly
+ *                reproducibly as the product over the set bits j of k (ascending) of
+ *                w_j = e^{2 pi i 2^j / 2^30}; the w_j come from the half-angle recurrence
+ *                cos(t/2) = sqrt((1 + cos t)/2), sin(t/2) = sin t / (2 cos(t/2)) started at
+ *                e^{i pi/2} = i, e^{i pi} = -1 (IEEE sqrt, division and products only)
  *   unit       : xi_r = e_j with j = (instance + r) mod N
  * so xi depends only on (seed, instance, r, i).  The estimator is normalised
  * by 1/(N R) for the random kinds and by 1/R for unit vectors.
@@ -87,6 +91,31 @@ void kpmo_philox4x64_10(const uint64_t ctr_in[4], const uint64_t key_in[2], uint
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
+/* w_j = e^{2 pi i 2^j / 2^30}, j = 0..29 (see the header comment). */
+#define PHASE_BITS 30
+static double phase_w[PHASE_BITS][2];
+static int phase_ready = 0;
+static void phase_table(void)
+{
+    if (phase_ready) return;
+    /* angle 2 pi / 2^m for m = 1 (pi), 2 (pi/2), ..., 30; w_j has m = 30 - j */
+    double c = -1.0, sn = 0.0;                 /* m = 1 */
+    phase_w[PHASE_BITS - 1][0] = c;
+    phase_w[PHASE_BITS - 1][1] = sn;
+    c = 0.0; sn = 1.0;                          /* m = 2 */
+    phase_w[PHASE_BITS - 2][0] = c;
+    phase_w[PHASE_BITS - 2][1] = sn;
+    for (int m = 3; m <= PHASE_BITS; ++m) {
+        double ch = sqrt((1.0 + c) / 2.0);
+        double sh = sn / (2.0 * ch);
+        c = ch;
+        sn = sh;
+        phase_w[PHASE_BITS - m][0] = c;
+        phase_w[PHASE_BITS - m][1] = sn;
+    }
+    phase_ready = 1;
+}
+
 /* Entry xi_{r,i} of the start vector, as (re, im). */
 static void start_entry(int vec_kind, uint64_t seed, uint64_t instance,
                         int64_t N, int64_t r, int64_t i, double *re, double *im)
@@ -106,16 +135,29 @@ static void start_entry(int vec_kind, uint64_t seed, uint64_t instance,
         *re = (word >> 63) ? -1.0 : 1.0;
         *im = 0.0;
     } else {
-        double u = (double)(word >> 11) * 0x1p-53;
-        double phi = 6.283185307179586 * u;
-        *re = cos(phi);
-        *im = sin(phi);
+        uint64_t k = word >> (64 - PHASE_BITS);
+        double zr = 1.0, zi = 0.0;
+        int started = 0;
+        for (int j = 0; j < PHASE_BITS; ++j) {
+            if (!((k >> j) & 1)) continue;
+            double wr = phase_w[j][0], wi = phase_w[j][1];
+            if (!started) {
+                zr = wr; zi = wi; started = 1;
+            } else {
+                double tr = zr * wr - zi * wi;
+                double ti = zr * wi + zi * wr;
+                zr = tr; zi = ti;
+            }
+        }
+        *re = zr;
+        *im = zi;
     }
 }
 
 void kpmo_start_vectors(int vec_kind, uint64_t seed, uint64_t instance, int64_t N, int R,
                         double *re /* [R][N] */, double *im /* [R][N] */)
 {
+    phase_table();
     for (int64_t r = 0; r < R; ++r)
         for (int64_t i = 0; i < N; ++i)
             start_entry(vec_kind, seed, instance, N, r, i, &re[r * N + i], &im[r * N + i]);
@@ -348,6 +390,7 @@ static int run_moments(const oper *op, int M, int R, int vec_kind, uint64_t seed
     int64_t N = op->N;
     if (M < 1 || R < 1 || N < 1) return KPMO_ERR_ARG;
     int K = M / 2;                       /* highest vector index formula B needs */
+    phase_table();
     int nmax = mu_A ? (M - 1 > K ? M - 1 : K) : K;
     dd *Snn = (dd *)calloc((size_t)nmax + 2, sizeof(dd));
     dd *Snm = (dd *)calloc((size_t)nmax + 2, sizeof(dd));

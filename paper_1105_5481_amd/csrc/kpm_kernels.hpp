@@ -41,7 +41,7 @@ namespace kpm {
 
 enum OpKind { OP_REAL2 = 0, OP_REAL3 = 1, OP_SPIN2 = 2, OP_SPIN3 = 3, OP_CSR_R = 4, OP_CSR_C = 5, OP_COUNT = 6 };
 enum { VEC_RADEMACHER = 0, VEC_PHASE = 1, VEC_UNIT = 2 };
-enum { MODE_FLAT = 0, MODE_MARCH = 1 };
+enum { MODE_FLAT = 0, MODE_MARCH = 1, MODE_SMALL = 2 };
 constexpr int BLOCK = 256;
 constexpr uint32_t XCD_MIN_ITEMS = 64;   // below this an instance's items are not split per XCD
 
@@ -200,10 +200,10 @@ template <> struct Dots<float> {
 
 // Sum (x0 + x1, x2 + x3) over the block in a fixed order; thread 0 stores
 // the four doubles (hi, lo, hi, lo) at dst.
-template <bool DD>
+template <bool DD, int NT = BLOCK>
 __device__ __forceinline__ void block_reduce_store(double x0, double x1, double x2, double x3, double *dst)
 {
-    __shared__ double red[BLOCK / 64][4];
+    __shared__ double red[NT / 64][4];
     if (DD) {
         dd a = dd_fast_two_sum(x0, x1), b = dd_fast_two_sum(x2, x3);
 #pragma unroll
@@ -231,7 +231,7 @@ __device__ __forceinline__ void block_reduce_store(double x0, double x1, double 
     if (threadIdx.x == 0) {
         dd a{red[0][0], red[0][1]}, b{red[0][2], red[0][3]};
 #pragma unroll
-        for (int k = 1; k < BLOCK / 64; ++k) {
+        for (int k = 1; k < NT / 64; ++k) {
             if (DD) {
                 a = dd_add(a, dd{red[k][0], red[k][1]});
                 b = dd_add(b, dd{red[k][2], red[k][3]});
@@ -296,6 +296,14 @@ __device__ __forceinline__ void start_words(uint64_t seed, uint64_t instance, ui
     philox4x64_10(c0, c1, c2, c3, seed, 4);
     w[0] = c0; w[1] = c1; w[2] = c2; w[3] = c3;
 }
+// Random phases: xi = e^{i phi}, phi = 2 pi k / 2^30 with k = word >> 34,
+// formed as the ordered product (ascending j) of w_j = e^{2 pi i 2^j / 2^30}
+// over the set bits of k.  The factors are computed on the host from the
+// half-angle recurrence with IEEE operations only and placed in constant
+// memory, so the phases are reproducible bit for bit on any IEEE machine.
+constexpr int PHASE_BITS = 30;
+__constant__ double kpm_phase_w[PHASE_BITS][2];
+
 // (re, im) of xi_{r,i} given its Philox word.
 __device__ __forceinline__ void start_value(int vec, uint64_t word, uint64_t instance, uint32_t N, uint32_t i,
                                             uint32_t r, double &re, double &im)
@@ -304,9 +312,25 @@ __device__ __forceinline__ void start_value(int vec, uint64_t word, uint64_t ins
         re = (word >> 63) ? -1.0 : 1.0;
         im = 0.0;
     } else if (vec == VEC_PHASE) {
-        double u = (double)(word >> 11) * 0x1p-53;
-        double phi = 6.283185307179586 * u;
-        sincos(phi, &im, &re);
+        const uint32_t k = (uint32_t)(word >> (64 - PHASE_BITS));
+        double zr = 1.0, zi = 0.0;
+        bool started = false;
+        for (int j = 0; j < PHASE_BITS; ++j) {
+            if (!((k >> j) & 1u)) continue;
+            const double wr = kpm_phase_w[j][0], wi = kpm_phase_w[j][1];
+            if (!started) {
+                zr = wr;
+                zi = wi;
+                started = true;
+            } else {
+                const double tr = zr * wr - zi * wi;
+                const double ti = zr * wi + zi * wr;
+                zr = tr;
+                zi = ti;
+            }
+        }
+        re = zr;
+        im = zi;
     } else {
         uint64_t j = (instance + (uint64_t)r) % (uint64_t)N;
         re = (j == (uint64_t)i) ? 1.0 : 0.0;
@@ -679,13 +703,140 @@ __global__ __launch_bounds__(BLOCK) void k_step_flat(const Inst *__restrict__ ta
 }
 
 // ---------------------------------------------------------------------------
+// the whole solve of a small instance inside one workgroup
+// ---------------------------------------------------------------------------
+// Both vector blocks live in LDS (2 * N * C * 16 bytes <= the LDS of one CU),
+// so the recursion never touches HBM; one block per instance, all steps in one
+// launch, the block barrier of the per-step dot reduction separating steps.
+// The per-step dots go straight to the instance's dots array.
+constexpr int SMALL_BLOCK = 1024;
+
+template <typename S, int OPK>
+__device__ __forceinline__ typename V16<S>::T small_elem(const Inst &I, uint32_t e, const typename V16<S>::T *cur,
+                                                         S hop)
+{
+    typedef typename V16<S>::T T;
+    typedef Mem<S, false> G;
+    typedef typename Mem<S, false>::S2 S2;
+    typedef Arith<S> A;
+    constexpr int W = V16<S>::W;
+    const uint32_t C = I.C;
+    const uint32_t i = fdiv(e, I.fC);
+    const uint32_t c = e - i * C;
+    const T v = cur[e];
+    T out;
+    if constexpr (OPK <= OP_SPIN3) {
+        constexpr bool D3 = (OPK == OP_REAL3 || OPK == OP_SPIN3);
+        constexpr bool SPIN = (OPK == OP_SPIN2 || OPK == OP_SPIN3);
+        constexpr int DIM = D3 ? 3 : 2;
+        constexpr int NS = 2 * DIM;
+        const uint32_t Lx = I.Lx, Ly = I.Ly;
+        const uint32_t yq = fdiv(i, I.fLx);
+        const uint32_t x = i - yq * Lx;
+        uint32_t y = yq, z = 0;
+        if (D3) {
+            z = fdiv(yq, I.fLy);
+            y = yq - z * Ly;
+        }
+        uint32_t nbi[NS];
+        nbi[0] = (x == 0) ? i + (Lx - 1) : i - 1;
+        nbi[1] = (x == Lx - 1) ? i - (Lx - 1) : i + 1;
+        nbi[2] = (y == 0) ? i + (Ly - 1) * Lx : i - Lx;
+        nbi[3] = (y == Ly - 1) ? i - (Ly - 1) * Lx : i + Lx;
+        if (D3) {
+            const uint32_t Pz = Lx * Ly, Lz = I.Lz;
+            nbi[4] = (z == 0) ? i + (Lz - 1) * Pz : i - Pz;
+            nbi[5] = (z == Lz - 1) ? i - (Lz - 1) * Pz : i + Pz;
+        }
+        T nb[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) nb[s] = cur[nbi[s] * C + c];
+        const bool hd = I.has_diag;
+        const S d = hd ? G::lds(I.diag, i) : (S)0;
+        if (!SPIN) {
+            out = apply_real<S, NS>(hd, d, hop, v, nb);
+        } else {
+            S hr[NS], hi[NS];
+#pragma unroll
+            for (int ax = 0; ax < DIM; ++ax) {
+                const S2 bm = G::ldc(I.bond, nbi[2 * ax] * DIM + ax);
+                const S2 bp = G::ldc(I.bond, i * DIM + ax);
+                hr[2 * ax] = bm[0]; hi[2 * ax] = -bm[1];
+                hr[2 * ax + 1] = bp[0]; hi[2 * ax + 1] = bp[1];
+            }
+            out = apply_cplx<S, NS>(hd, d, v, nb, hr, hi);
+        }
+    } else {
+        const int64_t kb = I.row_ptr[i], ke = I.row_ptr[i + 1];
+        const S d = G::lds(I.diag, i);
+        T a;
+#pragma unroll
+        for (int l = 0; l < W; ++l) a[l] = d * v[l];
+        for (int64_t kk = kb; kk < ke; ++kk) {
+            const uint32_t jj = (uint32_t)I.col[kk];
+            if (jj == i) continue;
+            const T vj = cur[jj * C + c];
+            if constexpr (OPK == OP_CSR_R) {
+                a = A::mac(a, ((const S *)I.val)[kk], vj);
+            } else {
+                const S hr = ((const S *)I.val)[2 * kk], hi = ((const S *)I.val)[2 * kk + 1];
+#pragma unroll
+                for (int l = 0; l < W / 2; ++l) {
+                    S ar = a[2 * l], ai = a[2 * l + 1];
+                    A::cmac(ar, ai, hr, hi, vj[2 * l], vj[2 * l + 1]);
+                    a[2 * l] = ar;
+                    a[2 * l + 1] = ai;
+                }
+            }
+        }
+        out = a;
+    }
+    return out;
+}
+
+template <typename S, int OPK>
+__global__ __launch_bounds__(SMALL_BLOCK) void k_solve_small(const Inst *__restrict__ tab)
+{
+    typedef typename V16<S>::T T;
+    extern __shared__ __align__(16) char kpm_lds[];
+    const Inst I = tab[blockIdx.x];
+    T *b0 = reinterpret_cast<T *>(kpm_lds);
+    T *b1 = b0 + I.nel;
+    S hop = 0;
+    if (OPK == OP_REAL2 || OPK == OP_REAL3) hop = Mem<S, false>::lds(I.hop, 0);
+    {
+        Dots<S> acc;
+        for (uint32_t e = threadIdx.x; e < I.nel; e += SMALL_BLOCK) {
+            const uint32_t i = fdiv(e, I.fC), c = e - i * I.C;
+            const T v = start_chunk<S>(I, i, c);
+            b0[e] = v;
+            acc.norm_only(v);
+        }
+        block_reduce_store<Dots<S>::DD, SMALL_BLOCK>(acc.s0, acc.c0, acc.s1, acc.c1, I.dots);
+    }
+    for (int32_t n = 0; n < I.K; ++n) {
+        const T *cur = (n & 1) ? b1 : b0;
+        T *nxt = (n & 1) ? b0 : b1;
+        Dots<S> acc;
+        for (uint32_t e = threadIdx.x; e < I.nel; e += SMALL_BLOCK) {
+            T out = small_elem<S, OPK>(I, e, cur, hop);
+            if (n > 0) out = (S)2 * out - nxt[e];
+            nxt[e] = out;
+            acc.add(out, cur[e]);
+        }
+        // the reduction's barriers also order this step's LDS writes before the next step's reads
+        block_reduce_store<Dots<S>::DD, SMALL_BLOCK>(acc.s0, acc.c0, acc.s1, acc.c1, I.dots + (size_t)(n + 1) * 4);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // reduction of the per-item partials and the moments
 // ---------------------------------------------------------------------------
 // Block (x, h): dots index idx = step0 + 1 + klo + x of instance h, for x < nk.
 __global__ __launch_bounds__(BLOCK) void k_reduce(const Inst *__restrict__ tab, int32_t klo, int32_t nk)
 {
     const Inst *I = tab + blockIdx.y;
-    if ((int32_t)blockIdx.x >= nk) return;
+    if ((int32_t)blockIdx.x >= nk || I->mode == MODE_SMALL) return;   // small solves write their dots directly
     const int32_t idx = I->step0 + 1 + klo + (int32_t)blockIdx.x;
     if (idx < 0 || idx > I->K) return;
     const double *p = I->partial + (size_t)(idx % I->pslots) * I->tiles * 4;

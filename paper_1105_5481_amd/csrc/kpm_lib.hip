@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -22,6 +23,23 @@ int g_march = 1;                        // lattices use the march kernels
 int g_march_items = 1024;               // target work items per instance when choosing march segments
 int g_xcd_split = 0;                    // 0 automatic, 1 by column tiles, 2 by segments, 3 none
 int g_alternate = 1;                    // march: odd segments walk downwards
+int g_small = 1;                        // solves whose two vector blocks fit in LDS run in one workgroup
+
+// Dynamic LDS one workgroup may use for the small-solve path (0 if no device).
+size_t small_lds_limit()
+{
+    static int cached_dev = -1;
+    static size_t cached = 0;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (dev != cached_dev) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) v = 0;
+        cached = v > 4096 ? (size_t)v - 4096 : 0;   // room for the static reduction scratch
+        cached_dev = dev;
+    }
+    return cached;
+}
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 inline hipStream_t S(void *s) { return (hipStream_t)s; }
@@ -30,6 +48,40 @@ kpm_status check_launch()
 {
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? KPM_OK : KPM_ERR_DEVICE;
+}
+
+// Phase factors w_j = e^{2 pi i 2^j / 2^30} (j = 0..29): angles 2 pi / 2^m for
+// m = 1 (exactly -1), 2 (exactly i), then cos(t/2) = sqrt((1 + cos t)/2) and
+// sin(t/2) = sin t / (2 cos(t/2)); w_j has m = 30 - j.  Uploaded to constant
+// memory once per device before the first kernel that draws start vectors.
+kpm_status ensure_phase_table()
+{
+    static std::mutex mu;
+    static bool done[64] = {false};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return KPM_ERR_DEVICE;
+    std::lock_guard<std::mutex> lock(mu);
+    if (done[dev]) return KPM_OK;
+    double w[PHASE_BITS][2];
+    double c = -1.0, sn = 0.0;
+    w[PHASE_BITS - 1][0] = c;
+    w[PHASE_BITS - 1][1] = sn;
+    c = 0.0;
+    sn = 1.0;
+    w[PHASE_BITS - 2][0] = c;
+    w[PHASE_BITS - 2][1] = sn;
+    for (int m = 3; m <= PHASE_BITS; ++m) {
+        const double ch = std::sqrt((1.0 + c) / 2.0);
+        const double sh = sn / (2.0 * ch);
+        c = ch;
+        sn = sh;
+        w[PHASE_BITS - m][0] = c;
+        w[PHASE_BITS - m][1] = sn;
+    }
+    if (hipMemcpyToSymbol(HIP_SYMBOL(kpm_phase_w), w, sizeof(w), 0, hipMemcpyHostToDevice) != hipSuccess)
+        return KPM_ERR_DEVICE;
+    done[dev] = true;
+    return KPM_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -392,7 +444,12 @@ bool make_plan(const kpm_ham *h, int32_t M, int32_t R, int32_t vec, Plan &p)
     // byte offsets beyond 32 bits need the 64-bit addressing variant
     const uint64_t bond_bytes = (uint64_t)h->N * (h->dim ? h->dim : 1) * 2 * p.esz;
     p.wide = (nel * 16 >= (1ull << 32) || bond_bytes >= (1ull << 32)) ? 1 : 0;
-    if (h->dim && g_march) {
+    const uint64_t small_bytes = 2ull * nel * 16;
+    if (g_small && small_bytes <= small_lds_limit()) {
+        p.mode = MODE_SMALL;
+        p.tiles = 1;
+        p.xcd = 0;
+    } else if (h->dim && g_march) {
         p.mode = MODE_MARCH;
         p.P = (uint32_t)(h->dim == 3 ? h->L[0] * h->L[1] : h->L[0]);
         p.Lm = (uint32_t)(h->dim == 3 ? h->L[2] : h->L[1]);
@@ -423,6 +480,11 @@ bool make_plan(const kpm_ham *h, int32_t M, int32_t R, int32_t vec, Plan &p)
     p.part_bytes = align256((size_t)p.P_slots * p.tiles * 4 * sizeof(double));
     p.dots_bytes = align256((size_t)(p.K + 1) * 4 * sizeof(double));
     p.buf_bytes = align256((size_t)h->N * p.Rs * p.esz);
+    if (p.mode == MODE_SMALL) {
+        p.part_bytes = 0;
+        p.buf_bytes = 0;
+        p.nb = 1;
+    }
     return true;
 }
 
@@ -490,6 +552,30 @@ kpm_status launch_step(int prec, int opk, int mode, int wide, const Inst *tab, c
     hipLaunchKernelGGL(get_step(prec, opk, mode, wide), dim3(blocks), dim3(BLOCK), 0, st, tab, map8, k);
     return check_launch();
 }
+typedef void (*small_fn)(const Inst *);
+template <typename S>
+small_fn small_for(int opk)
+{
+    switch (opk) {
+    case OP_REAL2: return k_solve_small<S, OP_REAL2>;
+    case OP_REAL3: return k_solve_small<S, OP_REAL3>;
+    case OP_SPIN2: return k_solve_small<S, OP_SPIN2>;
+    case OP_SPIN3: return k_solve_small<S, OP_SPIN3>;
+    case OP_CSR_R: return k_solve_small<S, OP_CSR_R>;
+    default: return k_solve_small<S, OP_CSR_C>;
+    }
+}
+// `count` small solves of one operator class, one workgroup each, with
+// `lds` bytes of dynamic LDS (the largest of the group).
+kpm_status launch_small(int prec, int opk, const Inst *tab, uint32_t count, size_t lds, hipStream_t st)
+{
+    small_fn f = prec == KPM_F64 ? small_for<double>(opk) : small_for<float>(opk);
+    if (hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return KPM_ERR_DEVICE;
+    hipLaunchKernelGGL(f, dim3(count), dim3(SMALL_BLOCK), lds, st, tab);
+    return check_launch();
+}
+
 kpm_status launch_reduce(const Inst *tab, int32_t count, int32_t klo, int32_t nk, hipStream_t st)
 {
     if (nk <= 0) return KPM_OK;
@@ -728,6 +814,7 @@ kpm_status kpm_solve_begin(kpm_ham *h, int32_t M, int32_t R, int32_t vec, uint64
     if (!out || !make_plan(h, M, R, vec, p)) return KPM_ERR_INVALID_ARG;
     const size_t need = align256(sizeof(Inst)) + instance_bytes(p);
     if (!ws || ((uintptr_t)ws & 255) || ws_bytes < need) return KPM_ERR_WORKSPACE;
+    if (ensure_phase_table() != KPM_OK) return KPM_ERR_DEVICE;
     kpm_solve *s = new (std::nothrow) kpm_solve();
     if (!s) return KPM_ERR_OUT_OF_MEMORY;
     hipStream_t st = S(stream);
@@ -737,6 +824,19 @@ kpm_status kpm_solve_begin(kpm_ham *h, int32_t M, int32_t R, int32_t vec, uint64
     fill_inst(h, p, M, R, vec, seed, instance, s->ws + align256(sizeof(Inst)), s->inst);
     kpm_status e = upload(s->tab_dev, &s->inst, sizeof(Inst), st);
     s->wide = p.wide;
+    if (p.mode == MODE_SMALL) {
+        // the whole recursion runs now; its dots are final
+        if (e == KPM_OK) e = launch_small(h->prec, h->opk, s->tab_dev, 1, 2 * (size_t)p.nel * 16, st);
+        s->next = p.K;
+        s->written = p.K + 1;
+        s->reduced = p.K + 1;
+        if (e != KPM_OK) {
+            delete s;
+            return e;
+        }
+        *out = s;
+        return KPM_OK;
+    }
     if (e == KPM_OK) e = launch_init(h->prec, p.wide, s->tab_dev, nullptr, p.nb, st);
     s->written = 1;
     s->reduced = 0;
@@ -891,6 +991,7 @@ kpm_status kpm_moments_batched(kpm_ham *const *h, int32_t count, const int32_t *
     for (int i = 0; i < count; ++i)
         if (!mu_dev[i]) return KPM_ERR_INVALID_ARG;
     if (!ws || ((uintptr_t)ws & 255) || ws_bytes < L.total) return KPM_ERR_WORKSPACE;
+    if (ensure_phase_table() != KPM_OK) return KPM_ERR_DEVICE;
     hipStream_t st = S(stream);
     char *base = (char *)ws;
     std::vector<Inst> tab(count);
@@ -922,8 +1023,15 @@ kpm_status kpm_moments_batched(kpm_ham *const *h, int32_t count, const int32_t *
     uint32_t *map_dev = (uint32_t *)(base + L.map_off);
     kpm_status e = upload(tab_dev, tab.data(), tab.size() * sizeof(Inst), st);
     if (e == KPM_OK && !map.empty()) e = upload(map_dev, map.data(), map.size() * 4, st);
-    for (size_t g = 0; g < L.gopk.size() && e == KPM_OK; ++g)
-        e = launch_init(L.prec, L.gwide[g], tab_dev + gfirst[g], map_dev + L.map_goff[g], L.gblocks[g], st);
+    for (size_t g = 0; g < L.gopk.size() && e == KPM_OK; ++g) {
+        if (L.gmode[g] == MODE_SMALL) {
+            size_t lds = 0;
+            for (int i : L.members[g]) lds = std::max(lds, 2 * (size_t)L.plans[i].nel * 16);
+            e = launch_small(L.prec, L.gopk[g], tab_dev + gfirst[g], (uint32_t)L.members[g].size(), lds, st);
+        } else {
+            e = launch_init(L.prec, L.gwide[g], tab_dev + gfirst[g], map_dev + L.map_goff[g], L.gblocks[g], st);
+        }
+    }
     int32_t written = 1, reduced = 0;  // dots indices, in lockstep for every instance
     for (int32_t k = 0; k < Kmax && e == KPM_OK; ++k) {
         if (written - reduced >= PSLOTS_MAX) {
@@ -931,8 +1039,9 @@ kpm_status kpm_moments_batched(kpm_ham *const *h, int32_t count, const int32_t *
             reduced = written;
         }
         for (size_t g = 0; g < L.gopk.size() && e == KPM_OK; ++g)
-            e = launch_step(L.prec, L.gopk[g], L.gmode[g], L.gwide[g], tab_dev + gfirst[g], map_dev + L.map_goff[g],
-                            L.gblocks[g], k, st);
+            if (L.gmode[g] != MODE_SMALL)
+                e = launch_step(L.prec, L.gopk[g], L.gmode[g], L.gwide[g], tab_dev + gfirst[g], map_dev + L.map_goff[g],
+                                L.gblocks[g], k, st);
         written += 1;
     }
     if (e == KPM_OK) e = launch_reduce(tab_dev, count, reduced - 1, written - reduced, st);
@@ -956,6 +1065,7 @@ kpm_status kpm_start_vectors(int32_t vec, int32_t complex_layout, uint64_t seed,
         return KPM_ERR_INVALID_ARG;
     const uint64_t n = (uint64_t)N * R;
     const int cplx = (complex_layout || vec == KPM_VEC_PHASE) ? 1 : 0;
+    if (ensure_phase_table() != KPM_OK) return KPM_ERR_DEVICE;
     hipLaunchKernelGGL(k_export_start, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, S(stream), vec, cplx, seed,
                        instance, (uint32_t)N, (uint32_t)R, out_dev);
     return check_launch();
@@ -988,6 +1098,10 @@ kpm_status kpm_set_launch(int32_t key, int32_t value)
         if (value != 0 && value != 1) return KPM_ERR_INVALID_ARG;
         g_alternate = value;
         return KPM_OK;
+    case KPM_LAUNCH_SMALL:
+        if (value != 0 && value != 1) return KPM_ERR_INVALID_ARG;
+        g_small = value;
+        return KPM_OK;
     }
     return KPM_ERR_INVALID_ARG;
 }
@@ -1002,6 +1116,7 @@ kpm_status kpm_get_launch(int32_t key, int32_t *value)
     case KPM_LAUNCH_MARCH_ITEMS: *value = g_march_items; return KPM_OK;
     case KPM_LAUNCH_XCD_SPLIT: *value = g_xcd_split; return KPM_OK;
     case KPM_LAUNCH_ALTERNATE: *value = g_alternate; return KPM_OK;
+    case KPM_LAUNCH_SMALL: *value = g_small; return KPM_OK;
     }
     return KPM_ERR_INVALID_ARG;
 }

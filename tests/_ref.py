@@ -83,9 +83,42 @@ def numpy_philox_block(counter, key):
     return bg.random_raw(4)
 
 
+def phase_factors(bits=30):
+    """w_j = exp(2 pi i 2^j / 2^bits) by the half-angle recurrence from exp(i pi) and exp(i pi/2)."""
+    w = [None] * bits
+    c, s = -1.0, 0.0
+    w[bits - 1] = (c, s)
+    c, s = 0.0, 1.0
+    w[bits - 2] = (c, s)
+    for m in range(3, bits + 1):
+        ch = math.sqrt((1.0 + c) / 2.0)
+        s = s / (2.0 * ch)
+        c = ch
+        w[bits - m] = (c, s)
+    return w
+
+
+_W = phase_factors()
+
+
+def phase_of_word(w):
+    """exp(2 pi i k / 2^30), k = top 30 bits of w, as the ordered product of w_j over set bits."""
+    k = w >> 34
+    z = None
+    for j in range(30):
+        if (k >> j) & 1:
+            if z is None:
+                z = _W[j]
+            else:
+                zr, zi = z
+                wr, wi = _W[j]
+                z = (zr * wr - zi * wi, zr * wi + zi * wr)
+    return complex(*(z or (1.0, 0.0)))
+
+
 def start_vectors_numpy(kind, seed, instance, N, R):
     """The start vectors of the method drawn with numpy's Philox: counter (i, r//4, instance, 0),
-    key (seed, 4), word r % 4; Rademacher from the top bit, phase from the top 53 bits."""
+    key (seed, 4), word r % 4; Rademacher from the top bit, phase from the top 30 bits."""
     X = np.zeros((R, N), dtype=complex)
     for r in range(R):
         for i in range(N):
@@ -96,8 +129,7 @@ def start_vectors_numpy(kind, seed, instance, N, R):
             if kind == 0:
                 X[r, i] = -1.0 if (w >> 63) else 1.0
             else:
-                phi = 6.283185307179586 * ((w >> 11) * 2.0 ** -53)
-                X[r, i] = complex(math.cos(phi), math.sin(phi))
+                X[r, i] = phase_of_word(w)
     return X
 
 

@@ -52,20 +52,29 @@ def _cases():
 CASES = _cases()
 
 
+# execution paths: one workgroup with the vectors in LDS (small), march kernels, flat kernels
+PATHS = {"small": dict(small=1), "march": dict(small=0, march=1), "flat": dict(small=0, march=0)}
+
+
+@pytest.mark.parametrize("path", list(PATHS))
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
-def test_fp64_and_fp32_match_oracle(case):
+def test_fp64_and_fp32_match_oracle(case, path):
     name, op, M, R, vec = case
     lo, hi = gu.oracle_bounds(op)
     a, b = oracle.scale_from_bounds(lo, hi, 0.01)
     ref = gu.oracle_moments(op, a, b, M, R, vec, seed=777, instance=1)
-    g64 = gu.gpu_moments(op, a, b, kpm.F64, M, R, vec, seed=777, instance=1)
-    gu.assert_fp64(g64, ref, name)
-    g32 = gu.gpu_moments(op, a, b, kpm.F32, M, R, vec, seed=777, instance=1)
-    gu.assert_fp32(g32, ref, name)
+    with kpm.launch_settings(**PATHS[path]):
+        g64 = gu.gpu_moments(op, a, b, kpm.F64, M, R, vec, seed=777, instance=1)
+        gu.assert_fp64(g64, ref, f"{name} [{path}]")
+        g32 = gu.gpu_moments(op, a, b, kpm.F32, M, R, vec, seed=777, instance=1)
+        gu.assert_fp32(g32, ref, f"{name} [{path}]")
 
 
-def test_config1_full_fp64():
-    """2D 32x32, t=1, on-site uniform[-0.5, 0.5], Gershgorin bounds, M=256, R=8 +-1 vectors."""
+@pytest.mark.parametrize("path", list(PATHS))
+def test_config1_full_fp64(path):
+    """2D 32x32, t=1, on-site uniform[-0.5, 0.5], Gershgorin bounds, M=256, R=8 +-1 vectors, and its
+    Jackson DoS on 1024 Chebyshev points."""
+    import torch
     cfg = wl.config1()
     op = cfg["lattice"]
     lo, hi = gu.oracle_bounds(op)
@@ -73,9 +82,15 @@ def test_config1_full_fp64():
     assert (glo, ghi) == (lo, hi)
     a, b = oracle.scale_from_bounds(lo, hi, 0.01)
     ref = gu.oracle_moments(op, a, b, cfg["M"], cfg["R"], cfg["vec"], cfg["seed"])
-    g = gu.gpu_moments(op, a, b, kpm.F64, cfg["M"], cfg["R"], cfg["vec"], cfg["seed"])
-    gu.assert_fp64(g, ref, "config1")
+    with kpm.launch_settings(**PATHS[path]):
+        g = gu.gpu_moments(op, a, b, kpm.F64, cfg["M"], cfg["R"], cfg["vec"], cfg["seed"])
+        g32 = gu.gpu_moments(op, a, b, kpm.F32, cfg["M"], cfg["R"], cfg["vec"], cfg["seed"])
+    gu.assert_fp64(g, ref, f"config1 [{path}]")
+    gu.assert_fp32(g32, ref, f"config1 f32 [{path}]")
     assert g[0] == 1.0
+    om_ref, rho_ref = oracle.dos(ref, cfg["K"], a, b)
+    om, rho = kpm.dos(torch.from_numpy(g).cuda(), cfg["K"], a, b)
+    assert np.abs(rho.cpu().numpy() - rho_ref).max() <= 1e-12 * np.abs(rho_ref).max()
 
 
 @pytest.mark.parametrize("vec", [0, 1, 2])
@@ -84,13 +99,7 @@ def test_start_vectors_match_oracle(vec):
     ref = oracle.start_vectors(vec, seed, inst, N, R).T              # (N, R) complex
     g = kpm.start_vectors(vec, True, seed, inst, N, R).cpu().numpy()
     gz = g[..., 0] + 1j * g[..., 1]
-    if vec == 1:
-        # the two sides evaluate cos/sin with different math libraries
-        err = np.abs(gz - ref).max()
-        print(f"  phase start vectors: max |d| = {err:.3e}")
-        assert err <= 4.5e-16
-    else:
-        assert np.array_equal(gz, ref)
+    assert np.array_equal(gz, ref)
 
 
 def test_gershgorin_matches_oracle():
