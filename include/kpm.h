@@ -178,6 +178,34 @@ kpm_status kpm_moments_batched(kpm_ham *const *h, int32_t count, const int32_t *
                                const uint64_t *instance, void *workspace_dev, size_t ws_bytes,
                                double *const *mu_dev, void *stream);
 
+/* Steps a begun solve still has to run (0 once all floor(M/2) products are done). */
+kpm_status kpm_solve_remaining(const kpm_solve *s, int32_t *remaining);
+
+/* Host-only size query for admission control: device bytes that kpm_build plus one
+ * solve of (M, R, vec) would occupy (operator + workspace); 0 on invalid input. */
+size_t kpm_request_bytes(const kpm_ham_desc *desc, int32_t prec, int32_t M, int32_t R, int32_t vec);
+/* Device bytes the operator of a built handle occupies. */
+size_t kpm_ham_bytes(const kpm_ham *h);
+
+/* Dynamic batches (continuous batching, the serving pattern of the north-star's
+ * point (3)): a set of begun solves (kpm_solve_begin) that advance together.
+ * kpm_batch_advance enqueues up to `steps` (<= 64) recursion steps in which
+ * every launch covers all member solves of one operator class, each at its own
+ * step n, so solves that joined at different times share launches; members
+ * that have run all their steps are skipped.  Solves join (kpm_batch_add) and
+ * leave (kpm_batch_remove) between calls; a solve that has left is finished
+ * with kpm_solve_finish as usual.  Results are bitwise equal to the same solve
+ * run alone (per-work-item partials).  All members share the recursion
+ * precision.  The batch owns a small device table (one hipMalloc in create).
+ * Calls on one batch must be serialised and use one stream. */
+typedef struct kpm_batch kpm_batch;
+kpm_status kpm_batch_create(int32_t capacity, kpm_batch **out);
+kpm_status kpm_batch_add(kpm_batch *b, kpm_solve *s);
+kpm_status kpm_batch_remove(kpm_batch *b, kpm_solve *s);
+int32_t kpm_batch_size(const kpm_batch *b);
+kpm_status kpm_batch_advance(kpm_batch *b, int32_t steps, void *stream);
+void kpm_batch_free(kpm_batch *b);
+
 /* Density of states, Eq. (fKPM), on the K first-kind Chebyshev points
  * x_k = cos(pi (k + 1/2)/K), k = 0..K-1, in FP64 on the device:
  *   rho(omega_k) = [g_0 mu_0 + 2 sum_{n=1}^{M-1} g_n mu_n cos(n theta_k)] / (pi a sin(theta_k)),

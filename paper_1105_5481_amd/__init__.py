@@ -74,6 +74,15 @@ def lib():
         "kpm_set_launch": (i32, [i32, i32]),
         "kpm_get_launch": (i32, [i32, P]),
         "kpm_selftest_fastdiv": (i32, [ctypes.c_uint32, P, i32]),
+        "kpm_solve_remaining": (i32, [P, P]),
+        "kpm_request_bytes": (sz, [pdesc, i32, i32, i32, i32]),
+        "kpm_ham_bytes": (sz, [P]),
+        "kpm_batch_create": (i32, [i32, P]),
+        "kpm_batch_add": (i32, [P, P]),
+        "kpm_batch_remove": (i32, [P, P]),
+        "kpm_batch_size": (i32, [P]),
+        "kpm_batch_advance": (i32, [P, i32, P]),
+        "kpm_batch_free": (None, [P]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(L, name)
@@ -276,6 +285,12 @@ class Solve:
                                      _stream(stream), ctypes.byref(s)), "kpm_solve_begin")
         self._s = s
 
+    @property
+    def remaining(self) -> int:
+        rem = ctypes.c_int32()
+        _check(lib().kpm_solve_remaining(self._s, ctypes.byref(rem)), "kpm_solve_remaining")
+        return rem.value
+
     def advance(self, steps: int, stream=None) -> int:
         rem = ctypes.c_int32()
         _check(lib().kpm_solve_advance(self._s, steps, _stream(stream), ctypes.byref(rem)), "kpm_solve_advance")
@@ -297,6 +312,61 @@ class Solve:
             self.close()
         except Exception:
             pass
+
+
+class Batch:
+    """A dynamic batch of begun solves advanced together (continuous batching)."""
+
+    def __init__(self, capacity: int = 256):
+        b = ctypes.c_void_p()
+        _check(lib().kpm_batch_create(capacity, ctypes.byref(b)), "kpm_batch_create")
+        self._b = b
+        self.members = []
+
+    def add(self, solve: "Solve"):
+        _check(lib().kpm_batch_add(self._b, solve._s), "kpm_batch_add")
+        self.members.append(solve)
+
+    def remove(self, solve: "Solve"):
+        _check(lib().kpm_batch_remove(self._b, solve._s), "kpm_batch_remove")
+        self.members.remove(solve)
+
+    def advance(self, steps: int, stream=None):
+        _check(lib().kpm_batch_advance(self._b, steps, _stream(stream)), "kpm_batch_advance")
+
+    def __len__(self):
+        return int(lib().kpm_batch_size(self._b))
+
+    def free(self):
+        if getattr(self, "_b", None) is not None and self._b.value:
+            lib().kpm_batch_free(self._b)
+        self._b = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def request_bytes(op, prec: int, M: int, R: int, vec: int) -> int:
+    """Device bytes an operator plus one solve of (M, R, vec) would occupy (host-only query)."""
+    d = HamDesc()
+    if hasattr(op, "row_ptr"):
+        d.kind, d.n, d.nnz = KIND_CSR, int(op.n), int(op.row_ptr[-1])
+        d.row_ptr_dev = 1                      # only checked for presence
+        d.col_dev = d.val_re_dev = 1 if d.nnz else None
+        d.val_im_dev = 1 if op.val_im is not None else None
+    else:
+        d.kind = KIND_CUBIC_3D if op.dim == 3 else KIND_SQUARE_2D
+        d.hop = int(op.hop)
+        d.L[0], d.L[1], d.L[2] = int(op.L[0]), int(op.L[1]), int(op.L[2]) if op.dim == 3 else 1
+        d.t = float(op.t)
+        d.spinor_dev = 1 if op.spinor is not None else None
+    n = lib().kpm_request_bytes(ctypes.byref(d), prec, M, R, vec)
+    if n == 0:
+        raise KPMError("invalid request shape")
+    return int(n)
 
 
 def dos(mu, K: int, a: float, b: float, jackson: bool = True, stream=None):

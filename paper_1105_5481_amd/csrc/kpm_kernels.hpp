@@ -66,6 +66,7 @@ struct Inst {
     int32_t M, K, R, vec;
     int32_t step0;     // recursion step n = step0 + (launch offset k)
     int32_t pslots;    // ring slots of partials
+    int32_t red_lo, red_n;  // dots indices [red_lo, red_lo + red_n) to reduce (k_reduce_ranges)
     uint64_t seed, instance;
     double norm;       // N R (random kinds) or R (unit vectors)
     const void *diag;  // S[N]
@@ -838,6 +839,22 @@ __global__ __launch_bounds__(BLOCK) void k_reduce(const Inst *__restrict__ tab, 
     const Inst *I = tab + blockIdx.y;
     if ((int32_t)blockIdx.x >= nk || I->mode == MODE_SMALL) return;   // small solves write their dots directly
     const int32_t idx = I->step0 + 1 + klo + (int32_t)blockIdx.x;
+    if (idx < 0 || idx > I->K) return;
+    const double *p = I->partial + (size_t)(idx % I->pslots) * I->tiles * 4;
+    dd a{0.0, 0.0}, b{0.0, 0.0};
+    for (uint32_t t = threadIdx.x; t < I->tiles; t += BLOCK) {
+        a = dd_add(a, dd{p[(size_t)t * 4 + 0], p[(size_t)t * 4 + 1]});
+        b = dd_add(b, dd{p[(size_t)t * 4 + 2], p[(size_t)t * 4 + 3]});
+    }
+    block_reduce_store<true>(a.hi, a.lo, b.hi, b.lo, I->dots + (size_t)idx * 4);
+}
+
+// Block (x, h): dots index red_lo + x of instance h, for x < red_n.
+__global__ __launch_bounds__(BLOCK) void k_reduce_ranges(const Inst *__restrict__ tab)
+{
+    const Inst *I = tab + blockIdx.y;
+    if ((int32_t)blockIdx.x >= I->red_n || I->mode == MODE_SMALL) return;
+    const int32_t idx = I->red_lo + (int32_t)blockIdx.x;
     if (idx < 0 || idx > I->K) return;
     const double *p = I->partial + (size_t)(idx % I->pslots) * I->tiles * 4;
     dd a{0.0, 0.0}, b{0.0, 0.0};

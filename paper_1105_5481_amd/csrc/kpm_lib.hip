@@ -396,6 +396,7 @@ struct kpm_ham {
     double a, b, t;
     int cplx_op, has_diag;
     char *mem;
+    size_t mem_bytes;
     void *diag, *bond, *hopv, *val;
     int64_t *row_ptr;
     int32_t *col;
@@ -716,6 +717,47 @@ static kpm_status prep_launch(kpm_ham *h, const kpm_ham_desc *d, double a, doubl
     return check_launch();
 }
 
+// Geometry and device-memory layout of the operator (no allocation).
+struct HamLayout {
+    size_t o_diag, o_val, o_rp, o_col, o_flag, o_hop, o_bond, bytes;
+};
+static void ham_layout(const kpm_ham_desc *d, int32_t prec, kpm_ham &h, HamLayout &L)
+{
+    std::memset(&L, 0, sizeof(L));
+    h.kind = d->kind;
+    h.hop = d->hop;
+    h.prec = prec;
+    const size_t esz = prec == KPM_F64 ? 8 : 4;
+    if (d->kind == KPM_CSR) {
+        h.dim = 0;
+        h.N = d->n;
+        h.nnz = d->nnz;
+        h.L[0] = d->n; h.L[1] = 1; h.L[2] = 1;
+        h.cplx_op = d->val_im_dev ? 1 : 0;
+        h.opk = h.cplx_op ? OP_CSR_C : OP_CSR_R;
+        h.has_diag = 1;
+        L.o_diag = 0;
+        L.o_val = align256(L.o_diag + h.N * esz);
+        L.o_rp = align256(L.o_val + (size_t)h.nnz * esz * (h.cplx_op ? 2 : 1));
+        L.o_col = align256(L.o_rp + (size_t)(h.N + 1) * 8);
+        L.o_flag = align256(L.o_col + (size_t)h.nnz * 4 + 4);
+        L.bytes = L.o_flag + 256;
+    } else {
+        h.dim = d->kind == KPM_CUBIC_3D ? 3 : 2;
+        h.L[0] = d->L[0];
+        h.L[1] = d->L[1];
+        h.L[2] = h.dim == 3 ? d->L[2] : 1;
+        h.N = h.L[0] * h.L[1] * h.L[2];
+        const int spin = d->hop == KPM_HOP_SPIN;
+        h.cplx_op = spin;
+        h.opk = spin ? (h.dim == 3 ? OP_SPIN3 : OP_SPIN2) : (h.dim == 3 ? OP_REAL3 : OP_REAL2);
+        L.o_hop = 0;
+        L.o_diag = 256;
+        L.o_bond = align256(L.o_diag + h.N * esz);
+        L.bytes = align256(L.o_bond + (spin ? (size_t)h.N * h.dim * 2 * esz : 0)) + 256;
+    }
+}
+
 kpm_status kpm_build(const kpm_ham_desc *d, double a, double b, int32_t prec, void *stream, kpm_ham **out)
 {
     if (!out || !valid_desc(d) || !(a > 0.0) || !std::isfinite(a) || !std::isfinite(b) ||
@@ -724,48 +766,23 @@ kpm_status kpm_build(const kpm_ham_desc *d, double a, double b, int32_t prec, vo
     hipStream_t st = S(stream);
     kpm_ham *h = new (std::nothrow) kpm_ham();
     if (!h) return KPM_ERR_OUT_OF_MEMORY;
-    h->kind = d->kind;
-    h->hop = d->hop;
-    h->prec = prec;
-    const size_t esz = prec == KPM_F64 ? 8 : 4;
-    size_t bytes = 0;
+    HamLayout L;
+    ham_layout(d, prec, *h, L);
+    if (hipMalloc((void **)&h->mem, L.bytes) != hipSuccess) {
+        delete h;
+        return KPM_ERR_OUT_OF_MEMORY;
+    }
+    h->mem_bytes = L.bytes;
     if (d->kind == KPM_CSR) {
-        h->dim = 0;
-        h->N = d->n;
-        h->nnz = d->nnz;
-        h->L[0] = d->n; h->L[1] = 1; h->L[2] = 1;
-        h->cplx_op = d->val_im_dev ? 1 : 0;
-        h->opk = h->cplx_op ? OP_CSR_C : OP_CSR_R;
-        h->has_diag = 1;
-        const size_t o_diag = 0;
-        const size_t o_val = align256(o_diag + h->N * esz);
-        const size_t o_rp = align256(o_val + (size_t)h->nnz * esz * (h->cplx_op ? 2 : 1));
-        const size_t o_col = align256(o_rp + (size_t)(h->N + 1) * 8);
-        const size_t o_flag = align256(o_col + (size_t)h->nnz * 4 + 4);
-        bytes = o_flag + 256;
-        if (hipMalloc((void **)&h->mem, bytes) != hipSuccess) { delete h; return KPM_ERR_OUT_OF_MEMORY; }
-        h->diag = h->mem + o_diag;
-        h->val = h->mem + o_val;
-        h->row_ptr = (int64_t *)(h->mem + o_rp);
-        h->col = (int32_t *)(h->mem + o_col);
-        h->flag = (int *)(h->mem + o_flag);
+        h->diag = h->mem + L.o_diag;
+        h->val = h->mem + L.o_val;
+        h->row_ptr = (int64_t *)(h->mem + L.o_rp);
+        h->col = (int32_t *)(h->mem + L.o_col);
+        h->flag = (int *)(h->mem + L.o_flag);
     } else {
-        h->dim = d->kind == KPM_CUBIC_3D ? 3 : 2;
-        h->L[0] = d->L[0];
-        h->L[1] = d->L[1];
-        h->L[2] = h->dim == 3 ? d->L[2] : 1;
-        h->N = h->L[0] * h->L[1] * h->L[2];
-        const int spin = d->hop == KPM_HOP_SPIN;
-        h->cplx_op = spin;
-        h->opk = spin ? (h->dim == 3 ? OP_SPIN3 : OP_SPIN2) : (h->dim == 3 ? OP_REAL3 : OP_REAL2);
-        const size_t o_hop = 0;
-        const size_t o_diag = 256;
-        const size_t o_bond = align256(o_diag + h->N * esz);
-        bytes = align256(o_bond + (spin ? (size_t)h->N * h->dim * 2 * esz : 0)) + 256;
-        if (hipMalloc((void **)&h->mem, bytes) != hipSuccess) { delete h; return KPM_ERR_OUT_OF_MEMORY; }
-        h->hopv = h->mem + o_hop;
-        h->diag = h->mem + o_diag;
-        h->bond = spin ? h->mem + o_bond : nullptr;
+        h->hopv = h->mem + L.o_hop;
+        h->diag = h->mem + L.o_diag;
+        h->bond = h->cplx_op ? h->mem + L.o_bond : nullptr;
     }
     kpm_status s = prep_launch(h, d, a, b, st);
     if (s != KPM_OK) {
@@ -776,6 +793,20 @@ kpm_status kpm_build(const kpm_ham_desc *d, double a, double b, int32_t prec, vo
     *out = h;
     return KPM_OK;
 }
+
+size_t kpm_request_bytes(const kpm_ham_desc *d, int32_t prec, int32_t M, int32_t R, int32_t vec)
+{
+    if (!valid_desc(d) || (prec != KPM_F64 && prec != KPM_F32)) return 0;
+    kpm_ham h;
+    std::memset(&h, 0, sizeof(h));
+    HamLayout L;
+    ham_layout(d, prec, h, L);
+    Plan p;
+    if (!make_plan(&h, M, R, vec, p)) return 0;
+    return L.bytes + align256(sizeof(Inst)) + instance_bytes(p);
+}
+
+size_t kpm_ham_bytes(const kpm_ham *h) { return h ? h->mem_bytes : 0; }
 
 kpm_status kpm_update(kpm_ham *h, const kpm_ham_desc *d, double a, double b, void *stream)
 {
@@ -1047,6 +1078,133 @@ kpm_status kpm_moments_batched(kpm_ham *const *h, int32_t count, const int32_t *
     if (e == KPM_OK) e = launch_reduce(tab_dev, count, reduced - 1, written - reduced, st);
     if (e == KPM_OK) e = launch_moments(tab_dev, count, Mmax, st);
     return e;
+}
+
+// ---------------------------------------------------------------------------
+// dynamic batches: begun solves advanced together, each at its own step
+// ---------------------------------------------------------------------------
+struct kpm_batch {
+    int32_t capacity;
+    char *mem;
+    size_t map_words;
+    std::vector<kpm_solve *> members;
+};
+
+kpm_status kpm_batch_create(int32_t capacity, kpm_batch **out)
+{
+    if (!out || capacity < 1 || capacity > 65535) return KPM_ERR_INVALID_ARG;
+    kpm_batch *b = new (std::nothrow) kpm_batch();
+    if (!b) return KPM_ERR_OUT_OF_MEMORY;
+    b->capacity = capacity;
+    b->map_words = (size_t)capacity * (size_t)std::max(g_max_blocks, 8192) / 8 + 8;
+    const size_t bytes = align256((size_t)capacity * sizeof(Inst)) + b->map_words * 4;
+    if (hipMalloc((void **)&b->mem, bytes) != hipSuccess) {
+        delete b;
+        return KPM_ERR_OUT_OF_MEMORY;
+    }
+    *out = b;
+    return KPM_OK;
+}
+
+void kpm_batch_free(kpm_batch *b)
+{
+    if (!b) return;
+    if (b->mem) (void)hipFree(b->mem);
+    delete b;
+}
+
+kpm_status kpm_batch_add(kpm_batch *b, kpm_solve *s)
+{
+    if (!b || !s) return KPM_ERR_INVALID_ARG;
+    if (std::find(b->members.begin(), b->members.end(), s) != b->members.end()) return KPM_ERR_INVALID_ARG;
+    if ((int32_t)b->members.size() >= b->capacity) return KPM_ERR_UNSUPPORTED;
+    if (!b->members.empty() && b->members[0]->h->prec != s->h->prec) return KPM_ERR_INVALID_ARG;
+    b->members.push_back(s);
+    return KPM_OK;
+}
+
+kpm_status kpm_batch_remove(kpm_batch *b, kpm_solve *s)
+{
+    if (!b || !s) return KPM_ERR_INVALID_ARG;
+    auto it = std::find(b->members.begin(), b->members.end(), s);
+    if (it == b->members.end()) return KPM_ERR_INVALID_ARG;
+    b->members.erase(it);
+    return KPM_OK;
+}
+
+int32_t kpm_batch_size(const kpm_batch *b) { return b ? (int32_t)b->members.size() : -1; }
+
+kpm_status kpm_solve_remaining(const kpm_solve *s, int32_t *remaining)
+{
+    if (!s || !remaining) return KPM_ERR_INVALID_ARG;
+    *remaining = s->inst.K - s->next;
+    return KPM_OK;
+}
+
+kpm_status kpm_batch_advance(kpm_batch *b, int32_t steps, void *stream)
+{
+    if (!b || steps < 0) return KPM_ERR_INVALID_ARG;
+    hipStream_t st = S(stream);
+    steps = std::min(steps, PSLOTS_MAX);   // after the reductions below every ring has room for PSLOTS_MAX
+    // active members grouped by kernel class; the table also carries each
+    // member's pending reduction range
+    std::vector<kpm_solve *> act;
+    for (kpm_solve *s : b->members)
+        if (s->inst.mode != MODE_SMALL && (s->next < s->inst.K || s->written > s->reduced)) act.push_back(s);
+    if (act.empty() || steps == 0) return KPM_OK;
+    std::vector<int> keys;
+    for (kpm_solve *s : act) {
+        const int key = kernel_key(s->inst.opk, s->inst.mode, s->wide);
+        if (std::find(keys.begin(), keys.end(), key) == keys.end()) keys.push_back(key);
+    }
+    std::vector<Inst> tab;
+    std::vector<uint32_t> map;
+    struct Group { int opk, mode, wide; uint32_t first, count, blocks; size_t map_off; };
+    std::vector<Group> groups;
+    int32_t max_red = 0;
+    for (int key : keys) {
+        Group g{0, 0, 0, (uint32_t)tab.size(), 0, 0, map.size()};
+        for (kpm_solve *s : act) {
+            if (kernel_key(s->inst.opk, s->inst.mode, s->wide) != key) continue;
+            Inst I = s->inst;
+            I.step0 = s->next;
+            I.block0 = g.blocks;
+            I.red_lo = s->reduced;
+            I.red_n = s->written - s->reduced;
+            max_red = std::max(max_red, I.red_n);
+            const uint32_t r = g.count;
+            for (uint32_t k = 0; k < I.nb / 8; ++k) map.push_back(r);
+            g.blocks += I.nb;
+            g.count += 1;
+            g.opk = I.opk;
+            g.mode = I.mode;
+            g.wide = s->wide;
+            tab.push_back(I);
+        }
+        groups.push_back(g);
+    }
+    if (map.size() > b->map_words) return KPM_ERR_UNSUPPORTED;
+    Inst *tab_dev = (Inst *)b->mem;
+    uint32_t *map_dev = (uint32_t *)(b->mem + align256((size_t)b->capacity * sizeof(Inst)));
+    kpm_status e = upload(tab_dev, tab.data(), tab.size() * sizeof(Inst), st);
+    if (e == KPM_OK && !map.empty()) e = upload(map_dev, map.data(), map.size() * 4, st);
+    if (e == KPM_OK && max_red > 0) {
+        hipLaunchKernelGGL(k_reduce_ranges, dim3(max_red, (uint32_t)tab.size()), dim3(BLOCK), 0, st, tab_dev);
+        e = check_launch();
+    }
+    const int prec = act[0]->h->prec;
+    for (int32_t k = 0; k < steps && e == KPM_OK; ++k)
+        for (const Group &g : groups)
+            if (e == KPM_OK)
+                e = launch_step(prec, g.opk, g.mode, g.wide, tab_dev + g.first, map_dev + g.map_off, g.blocks, k, st);
+    if (e != KPM_OK) return e;
+    for (kpm_solve *s : act) {
+        s->reduced = s->written;
+        const int32_t done = std::min(steps, s->inst.K - s->next);
+        s->next += done;
+        s->written += done;
+    }
+    return KPM_OK;
 }
 
 kpm_status kpm_dos(const double *mu_dev, int32_t M, int32_t jackson, int32_t K, double a, double b, double *omega_dev,
