@@ -85,6 +85,54 @@ def pmc_summary(root):
         print(f"{name} grid={grid}: {vals}")
 
 
+def serving_leg(n_requests, logN_max, load, seed=1005):
+    """Config-5 recipe (Poisson arrivals; N log-uniform from 2^12 up to 2^logN_max; 2D/3D; real or
+    spin hopping; M in {256, 1024, 4096, 8192}; R in [8, 64]).  Capacity of the batched FP32 server
+    is measured with every request present at t = 0; a wall-clock trace at `load` x capacity is then
+    served by it and replayed through the plain FP64 first-come-first-served path (one solve at a time)."""
+    import numpy as np
+    import paper_1105_5481_amd as kpm
+    from paper_1105_5481_amd import workloads as wl
+    from paper_1105_5481_amd.serve import KPMRequest, Server, latency_stats
+    stream = wl.config5_stream(n_requests, rate=1.0, seed=seed, logN_max=logN_max)
+
+    def reqs(arrivals):
+        return [KPMRequest(op=r.lattice, M=r.M, R=r.R, vec=r.vec, seed=r.seed, instance=0, arrival=t, rid=r.rid)
+                for r, t in zip(stream, arrivals)]
+
+    updates = float(sum(r.lattice.N * r.M * r.R for r in stream))
+    alg_bytes = 0.0
+    for r in stream:
+        cplx = r.lattice.hop == wl.HOP_SPIN or r.vec == wl.VEC_PHASE
+        alg_bytes += (r.M // 2) * algorithmic_bytes_per_step(r.lattice.N, r.R, cplx, 4, r.lattice.onsite is not None,
+                                                             r.lattice.dim if r.lattice.hop == wl.HOP_SPIN else 0)
+    srv = Server(prec=kpm.F32, max_active=64, chunk=32)
+    t0 = time.perf_counter()
+    res = srv.run(reqs([0.0] * n_requests), clock="chunks")
+    makespan = time.perf_counter() - t0
+    srv.close()
+    assert all(r.status == "ok" for r in res)
+    capacity = n_requests / makespan
+    gaps = np.diff([0.0] + [r.arrival for r in stream])
+    arrivals = np.cumsum(gaps / (load * capacity))
+    log(f"bench: serving capacity {capacity:.1f} req/s; trace of {n_requests} requests over {arrivals[-1]:.2f} s")
+    srv = Server(prec=kpm.F32, max_active=64, chunk=32)
+    served = srv.run(reqs(arrivals), clock="wall")
+    conc = srv.max_concurrent
+    srv.close()
+    srv = Server(prec=kpm.F64, max_active=1, chunk=64)
+    plain = srv.run(reqs(arrivals), clock="wall")
+    srv.close()
+    svc64 = np.array([r.t_done - r.t_admit for r in plain if r.status == "ok"])
+    return {"requests": n_requests, "logN_range": [12, logN_max], "offered_load": load,
+            "fp32_capacity_req_per_s": capacity, "fp32_throughput_updates_per_s": updates / makespan,
+            "fp32_throughput_GBps_algorithmic": alg_bytes / makespan / 1e9,
+            "fp32_served": latency_stats(served), "max_concurrent_solves": conc,
+            "fp64_fcfs": latency_stats(plain),
+            "fp64_isolated_service_ms": {"p50": float(np.percentile(svc64, 50) * 1e3),
+                                         "p99": float(np.percentile(svc64, 99) * 1e3)}}
+
+
 def cpu_baseline(lat, a, b, vec, seed):
     """The oracle (plain FP64 CPU code) on a bounded sample of the same lattice."""
     import oracle
@@ -107,6 +155,10 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=160)
+    ap.add_argument("--serve-logn-max", type=float, default=18.0)
+    ap.add_argument("--serve-load", type=float, default=0.7)
     ap.add_argument("--tpt", type=int, default=0, help="chunks per thread per tile (1, 2, 4)")
     ap.add_argument("--max-blocks", type=int, default=0)
     ap.add_argument("--march", type=int, default=-1, help="1: march kernels for lattices, 0: flat kernels")
@@ -249,6 +301,10 @@ def main():
                             "dtype": "c128" if cplx else "f64", "speedup_fp32_over_fp64": value / v64,
                             "fp32_max_abs_err_vs_fp64": float(np.abs(mu32 - mu64).max())}
         s64[0].free()
+
+    if not args.no_serve:
+        log("bench: serving leg")
+        out["serving"] = serving_leg(args.serve_requests, args.serve_logn_max, args.serve_load)
 
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on a bounded sample")

@@ -28,7 +28,7 @@ from . import F32, F64, VEC_RADEMACHER, Batch, Hamiltonian, KPMError, Solve, dos
     scale_from_bounds
 
 
-@dataclass
+@dataclass(eq=False)
 class KPMRequest:
     op: object                      # workloads.Lattice or workloads.CSR
     M: int
@@ -62,7 +62,7 @@ class KPMResult:
         return self.t_done - self.t_arrival
 
 
-@dataclass
+@dataclass(eq=False)
 class _Live:
     req: KPMRequest
     bytes: int
@@ -218,7 +218,8 @@ class Server:
             lv.ham.free()
             lv.solve = lv.ham = lv.mu = lv.om = lv.rho = None
             self.used -= lv.bytes
-        self.retiring = [lv for lv in self.retiring if lv not in done]
+        done_ids = {id(lv) for lv in done}
+        self.retiring = [lv for lv in self.retiring if id(lv) not in done_ids]
 
     def _finish_result(self, req, status, mu=None, omega=None, rho=None, t_admit=0.0, a=0.0, b=0.0, message=""):
         self.results[req.rid] = KPMResult(rid=req.rid, status=status, mu=mu, omega=omega, rho=rho, a=a, b=b,

@@ -108,6 +108,17 @@ def test_cancel():
     assert srv.results[0].status == "ok" and srv.results[2].status == "ok"
 
 
+def test_many_retire_together():
+    """Several solves finishing in the same chunk retire together."""
+    reqs = [KPMRequest(op=wl.square_lattice(90, W=1.0, seed=k), M=64, R=8, seed=k, arrival=0, rid=k) for k in range(6)]
+    srv = Server(prec=kpm.F32, max_active=8, chunk=64)
+    res = srv.run(reqs, clock="chunks")
+    srv.close()
+    assert [r.status for r in res] == ["ok"] * 6
+    for req, r in zip(reqs, res):
+        assert np.array_equal(r.mu, _solo(req, kpm.F32, r.a, r.b))
+
+
 def test_wall_clock_trace_latency():
     reqs = _requests()
     for k, r in enumerate(reqs):
