@@ -165,6 +165,7 @@ def main():
     ap.add_argument("--march-items", type=int, default=0)
     ap.add_argument("--xcd-split", type=int, default=-1, help="0 auto, 1 column tiles, 2 segments, 3 none")
     ap.add_argument("--alternate", type=int, default=-1)
+    ap.add_argument("--streaming", type=int, default=-1)
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain 1 GiB device copy three times (counter calibration under rocprofv3)")
     ap.add_argument("--pmc-summary", metavar="DIR",
@@ -200,7 +201,8 @@ def main():
     kpm.set_launch(elems_per_thread=args.tpt or None, max_blocks=args.max_blocks or None,
                    march=None if args.march < 0 else args.march, march_items=args.march_items or None,
                    xcd_split=None if args.xcd_split < 0 else args.xcd_split,
-                   alternate=None if args.alternate < 0 else args.alternate)
+                   alternate=None if args.alternate < 0 else args.alternate,
+                   streaming=None if args.streaming < 0 else args.streaming)
     dev = "cuda"
     stream = torch.cuda.current_stream()
 

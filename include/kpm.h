@@ -206,6 +206,20 @@ int32_t kpm_batch_size(const kpm_batch *b);
 kpm_status kpm_batch_advance(kpm_batch *b, int32_t steps, void *stream);
 void kpm_batch_free(kpm_batch *b);
 
+/* A whole batched solve (the same arguments as kpm_moments_batched) captured once
+ * into a hipGraph on `stream` (a non-default stream) and replayed with one
+ * kpm_graph_launch call: Monte-Carlo style loops re-prepare the operators with
+ * kpm_update between replays and replay the same launch sequence (same seeds and
+ * instances; the workspace and output arrays must stay valid for the graph's
+ * life).  The capture contains kernels only (no memset or host copies). */
+typedef struct kpm_graph kpm_graph;
+kpm_status kpm_graph_capture_batched(kpm_ham *const *h, int32_t count, const int32_t *M, const int32_t *R,
+                                     int32_t vec, const uint64_t *seed, const uint64_t *instance,
+                                     void *workspace_dev, size_t ws_bytes, double *const *mu_dev,
+                                     void *stream, kpm_graph **out);
+kpm_status kpm_graph_launch(kpm_graph *g, void *stream);
+void kpm_graph_free(kpm_graph *g);
+
 /* Density of states, Eq. (fKPM), on the K first-kind Chebyshev points
  * x_k = cos(pi (k + 1/2)/K), k = 0..K-1, in FP64 on the device:
  *   rho(omega_k) = [g_0 mu_0 + 2 sum_{n=1}^{M-1} g_n mu_n cos(n theta_k)] / (pi a sin(theta_k)),
@@ -234,6 +248,10 @@ kpm_status kpm_start_vectors(int32_t vec, int32_t complex_layout, uint64_t seed,
  *   KPM_LAUNCH_ALTERNATE         1: odd march segments walk downwards
  *   KPM_LAUNCH_SMALL             1: a solve whose two vector blocks fit in the LDS of one
  *                                compute unit runs entirely in one workgroup (one launch)
+ *   KPM_LAUNCH_STREAMING         march kernels: 1 = r_{n-1} read / r_{n+1} written with
+ *                                non-temporal hints, 0 = cached, 2 (default) = cached when
+ *                                vectors and operator take at most 192 MiB (they then stay
+ *                                in the 256 MiB Infinity Cache between steps), else 1
  * The partial sums of the dot products are formed per work item, so the
  * moments do not depend on the grid (MAX_BLOCKS) nor on the batch an instance
  * runs in; the other keys change the work items and with them the order in
@@ -246,7 +264,8 @@ typedef enum {
     KPM_LAUNCH_MARCH_ITEMS = 3,
     KPM_LAUNCH_XCD_SPLIT = 4,
     KPM_LAUNCH_ALTERNATE = 5,
-    KPM_LAUNCH_SMALL = 6
+    KPM_LAUNCH_SMALL = 6,
+    KPM_LAUNCH_STREAMING = 7
 } kpm_launch_key;
 kpm_status kpm_set_launch(int32_t key, int32_t value);
 kpm_status kpm_get_launch(int32_t key, int32_t *value);

@@ -83,6 +83,9 @@ def lib():
         "kpm_batch_size": (i32, [P]),
         "kpm_batch_advance": (i32, [P, i32, P]),
         "kpm_batch_free": (None, [P]),
+        "kpm_graph_capture_batched": (i32, [P, i32, P, P, i32, P, P, P, sz, P, P, P]),
+        "kpm_graph_launch": (i32, [P, P]),
+        "kpm_graph_free": (None, [P]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(L, name)
@@ -272,6 +275,50 @@ def moments_batched(hams: Sequence[Hamiltonian], M, R, vec: int = VEC_RADEMACHER
     return mus
 
 
+class BatchedGraph:
+    """A batched solve captured once into a hipGraph and replayed (kpm_graph_capture_batched).
+    `stream` must be a non-default torch.cuda.Stream; outputs land in self.mus on every replay."""
+
+    def __init__(self, hams: Sequence[Hamiltonian], M, R, vec: int, seeds, instances, stream):
+        torch = _torch()
+        n = len(hams)
+        self.hams = list(hams)
+        self.Ms = [int(M)] * n if isinstance(M, int) else [int(x) for x in M]
+        self.Rs = [int(R)] * n if isinstance(R, int) else [int(x) for x in R]
+        self._harr = (ctypes.c_void_p * n)(*[h.handle.value for h in hams])
+        self._marr = (ctypes.c_int32 * n)(*self.Ms)
+        self._rarr = (ctypes.c_int32 * n)(*self.Rs)
+        self._sarr = (ctypes.c_uint64 * n)(*list(seeds))
+        self._iarr = (ctypes.c_uint64 * n)(*list(instances))
+        nb = lib().kpm_workspace_bytes_batched(self._harr, n, self._marr, self._rarr, vec)
+        if nb == 0:
+            raise KPMError("invalid batch")
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=hams[0].device)
+        self.mus = [torch.empty(m, dtype=torch.float64, device=hams[0].device) for m in self.Ms]
+        self._parr = (ctypes.c_void_p * n)(*[m.data_ptr() for m in self.mus])
+        self.stream = stream
+        g = ctypes.c_void_p()
+        _check(lib().kpm_graph_capture_batched(self._harr, n, self._marr, self._rarr, vec, self._sarr, self._iarr,
+                                               self.ws.data_ptr(), nb, self._parr, _stream(stream), ctypes.byref(g)),
+               "kpm_graph_capture_batched")
+        self._g = g
+
+    def launch(self):
+        _check(lib().kpm_graph_launch(self._g, _stream(self.stream)), "kpm_graph_launch")
+        return self.mus
+
+    def free(self):
+        if getattr(self, "_g", None) is not None and self._g.value:
+            lib().kpm_graph_free(self._g)
+        self._g = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
 class Solve:
     """A chunked solve: begin -> advance(k) ... -> finish; the vector state stays in `workspace`."""
 
@@ -391,9 +438,9 @@ def start_vectors(vec: int, complex_layout: bool, seed: int, instance: int, N: i
 
 
 LAUNCH_ELEMS_PER_THREAD, LAUNCH_MAX_BLOCKS, LAUNCH_MARCH, LAUNCH_MARCH_ITEMS, LAUNCH_XCD_SPLIT, LAUNCH_ALTERNATE, \
-    LAUNCH_SMALL = range(7)
+    LAUNCH_SMALL, LAUNCH_STREAMING = range(8)
 _LAUNCH_KEYS = {"elems_per_thread": 0, "max_blocks": 1, "march": 2, "march_items": 3, "xcd_split": 4, "alternate": 5,
-                "small": 6}
+                "small": 6, "streaming": 7}
 
 
 def set_launch(**kw):

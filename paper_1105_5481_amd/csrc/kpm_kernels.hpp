@@ -52,6 +52,7 @@ struct Inst {
     int32_t mode;
     int32_t xcd;       // items split per XCD (0 none, 1 by units, 2 by segments)
     int32_t alt;       // march: odd segments walk downwards
+    int32_t nt;        // march: r_{n-1}/r_{n+1} accessed with non-temporal hints
     uint32_t Lx, Ly, Lz, N;
     FastDiv fLx, fLy, fC;
     uint32_t C;        // 16-byte chunks per site
@@ -101,6 +102,17 @@ template <typename S, bool WIDE> struct Mem {
     static __device__ __forceinline__ void st_nt(void *b, uint32_t chunk, T v)
     {
         __builtin_nontemporal_store(v, (KPM_GLOBAL T *)at(b, chunk));
+    }
+    // streamed access of r_{n-1} / r_{n+1}: non-temporal (NT) or cached
+    template <bool NT> static __device__ __forceinline__ T ld_s(const void *b, uint32_t chunk)
+    {
+        if (NT) return ld_nt(b, chunk);
+        return ld(b, chunk);
+    }
+    template <bool NT> static __device__ __forceinline__ void st_s(void *b, uint32_t chunk, T v)
+    {
+        if (NT) st_nt(b, chunk, v);
+        else st(b, chunk, v);
     }
     static __device__ __forceinline__ void st(void *b, uint32_t chunk, T v) { *(KPM_GLOBAL T *)at(b, chunk) = v; }
     // element e of an array of S
@@ -472,7 +484,7 @@ __device__ __forceinline__ typename V16<S>::T apply_cplx(bool hd, S d, typename 
 // ---------------------------------------------------------------------------
 // the fused recursion step, march form (lattices)
 // ---------------------------------------------------------------------------
-template <typename S, int OPK, bool WIDE>
+template <typename S, int OPK, bool WIDE, bool NT>
 __global__ __launch_bounds__(BLOCK) void k_step_march(const Inst *__restrict__ tab,
                                                       const uint32_t *__restrict__ map8, int32_t k)
 {
@@ -547,7 +559,7 @@ __global__ __launch_bounds__(BLOCK) void k_step_march(const Inst *__restrict__ t
                 nb[NS - 2] = down ? va : vb;
                 nb[NS - 1] = down ? vb : va;
                 T prev;
-                if (!first) prev = G::ld_nt(nxt, ch);
+                if (!first) prev = G::template ld_s<NT>(nxt, ch);
                 const S d = hd ? G::lds(I.diag, i) : (S)0;
                 T out;
                 if (!SPIN) {
@@ -575,7 +587,7 @@ __global__ __launch_bounds__(BLOCK) void k_step_march(const Inst *__restrict__ t
                     bb = ba;
                 }
                 if (!first) out = (S)2 * out - prev;
-                G::st_nt(nxt, ch, out);
+                G::template st_s<NT>(nxt, ch, out);
                 acc.add(out, v0);
                 vb = v0;
                 v0 = va;

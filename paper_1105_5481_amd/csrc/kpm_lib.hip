@@ -24,6 +24,8 @@ int g_march_items = 1024;               // target work items per instance when c
 int g_xcd_split = 0;                    // 0 automatic, 1 by column tiles, 2 by segments, 3 none
 int g_alternate = 1;                    // march: odd segments walk downwards
 int g_small = 1;                        // solves whose two vector blocks fit in LDS run in one workgroup
+int g_streaming = 2;                    // march: 0 cached, 1 non-temporal access of r_{n-1}/r_{n+1}, 2 by size
+constexpr uint64_t CACHE_RESIDENT_BYTES = 192ull << 20;   // below this the state stays in the 256 MiB Infinity Cache
 
 // Dynamic LDS one workgroup may use for the small-solve path (0 if no device).
 size_t small_lds_limit()
@@ -351,19 +353,22 @@ typedef void (*step_fn)(const Inst *, const uint32_t *, int32_t);
 typedef void (*init_fn)(const Inst *, const uint32_t *);
 
 // Kernel class of a solve: one launch covers instances of one class.
-inline int kernel_key(int opk, int mode, int wide) { return (opk * 2 + mode) * 2 + wide; }
+inline int kernel_key(int opk, int mode, int wide, int nt) { return ((opk * 4 + mode) * 2 + wide) * 2 + nt; }
 
-template <typename S, bool WIDE>
-step_fn step_for(int opk, int mode)
+template <typename S, bool WIDE, bool NT>
+step_fn march_for(int opk)
 {
-    if (mode == MODE_MARCH) {
-        switch (opk) {
-        case OP_REAL2: return k_step_march<S, OP_REAL2, WIDE>;
-        case OP_REAL3: return k_step_march<S, OP_REAL3, WIDE>;
-        case OP_SPIN2: return k_step_march<S, OP_SPIN2, WIDE>;
-        default: return k_step_march<S, OP_SPIN3, WIDE>;
-        }
+    switch (opk) {
+    case OP_REAL2: return k_step_march<S, OP_REAL2, WIDE, NT>;
+    case OP_REAL3: return k_step_march<S, OP_REAL3, WIDE, NT>;
+    case OP_SPIN2: return k_step_march<S, OP_SPIN2, WIDE, NT>;
+    default: return k_step_march<S, OP_SPIN3, WIDE, NT>;
     }
+}
+template <typename S, bool WIDE>
+step_fn step_for(int opk, int mode, int nt)
+{
+    if (mode == MODE_MARCH) return nt ? march_for<S, WIDE, true>(opk) : march_for<S, WIDE, false>(opk);
     switch (opk) {
     case OP_REAL2: return k_step_flat<S, OP_REAL2, WIDE>;
     case OP_REAL3: return k_step_flat<S, OP_REAL3, WIDE>;
@@ -373,10 +378,10 @@ step_fn step_for(int opk, int mode)
     default: return k_step_flat<S, OP_CSR_C, WIDE>;
     }
 }
-step_fn get_step(int prec, int opk, int mode, int wide)
+step_fn get_step(int prec, int opk, int mode, int wide, int nt)
 {
-    if (prec == KPM_F64) return wide ? step_for<double, true>(opk, mode) : step_for<double, false>(opk, mode);
-    return wide ? step_for<float, true>(opk, mode) : step_for<float, false>(opk, mode);
+    if (prec == KPM_F64) return wide ? step_for<double, true>(opk, mode, nt) : step_for<double, false>(opk, mode, nt);
+    return wide ? step_for<float, true>(opk, mode, nt) : step_for<float, false>(opk, mode, nt);
 }
 init_fn get_init(int prec, int wide)
 {
@@ -418,7 +423,7 @@ namespace {
 
 // Geometry of one solve: everything but device pointers.
 struct Plan {
-    int cplx, mode, wide, xcd, alt;
+    int cplx, mode, wide, xcd, alt, nt;
     uint32_t W, Rs, C, nel, tiles, nb;
     uint32_t P, Lm, S, nct, nseg;
     int32_t K, P_slots, tpt;
@@ -486,6 +491,10 @@ bool make_plan(const kpm_ham *h, int32_t M, int32_t R, int32_t vec, Plan &p)
         p.buf_bytes = 0;
         p.nb = 1;
     }
+    // r_{n+1} is read again as r_n by the next step: keep it cached when the
+    // whole state fits the Infinity Cache, stream it otherwise
+    const uint64_t state = 2ull * p.buf_bytes + (uint64_t)h->N * (h->dim ? (1 + 2 * h->dim) : 1) * p.esz;
+    p.nt = g_streaming == 2 ? (state > CACHE_RESIDENT_BYTES ? 1 : 0) : g_streaming;
     return true;
 }
 
@@ -514,6 +523,7 @@ void fill_inst(const kpm_ham *h, const Plan &p, int32_t M, int32_t R, int32_t ve
     I.mode = p.mode;
     I.xcd = p.xcd;
     I.alt = p.alt;
+    I.nt = p.nt;
     I.P = p.P;
     I.Lm = p.Lm;
     I.S = p.S;
@@ -547,10 +557,10 @@ kpm_status launch_init(int prec, int wide, const Inst *tab, const uint32_t *map8
     hipLaunchKernelGGL(get_init(prec, wide), dim3(blocks), dim3(BLOCK), 0, st, tab, map8);
     return check_launch();
 }
-kpm_status launch_step(int prec, int opk, int mode, int wide, const Inst *tab, const uint32_t *map8, uint32_t blocks,
-                       int32_t k, hipStream_t st)
+kpm_status launch_step(int prec, int opk, int mode, int wide, int nt, const Inst *tab, const uint32_t *map8,
+                       uint32_t blocks, int32_t k, hipStream_t st)
 {
-    hipLaunchKernelGGL(get_step(prec, opk, mode, wide), dim3(blocks), dim3(BLOCK), 0, st, tab, map8, k);
+    hipLaunchKernelGGL(get_step(prec, opk, mode, wide, nt), dim3(blocks), dim3(BLOCK), 0, st, tab, map8, k);
     return check_launch();
 }
 typedef void (*small_fn)(const Inst *);
@@ -571,7 +581,11 @@ small_fn small_for(int opk)
 kpm_status launch_small(int prec, int opk, const Inst *tab, uint32_t count, size_t lds, hipStream_t st)
 {
     small_fn f = prec == KPM_F64 ? small_for<double>(opk) : small_for<float>(opk);
-    if (hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess) return KPM_ERR_DEVICE;
+    if (cs == hipStreamCaptureStatusNone &&
+        hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)small_lds_limit()) !=
+            hipSuccess)
         return KPM_ERR_DEVICE;
     hipLaunchKernelGGL(f, dim3(count), dim3(SMALL_BLOCK), lds, st, tab);
     return check_launch();
@@ -873,7 +887,7 @@ kpm_status kpm_solve_begin(kpm_ham *h, int32_t M, int32_t R, int32_t vec, uint64
     s->reduced = 0;
     s->next = 0;
     if (e == KPM_OK && p.K >= 1) {
-        e = launch_step(h->prec, h->opk, p.mode, p.wide, s->tab_dev, nullptr, p.nb, 0, st);
+        e = launch_step(h->prec, h->opk, p.mode, p.wide, p.nt, s->tab_dev, nullptr, p.nb, 0, st);
         s->next = 1;
         s->written = 2;
     }
@@ -904,7 +918,7 @@ kpm_status kpm_solve_advance(kpm_solve *s, int32_t max_steps, void *stream, int3
     for (int32_t c = 0; c < max_steps && s->next < I.K && e == KPM_OK; ++c) {
         if (s->written - s->reduced >= I.pslots) e = solve_reduce_pending(s, st);
         if (e != KPM_OK) break;
-        e = launch_step(s->h->prec, I.opk, I.mode, s->wide, s->tab_dev, nullptr, I.nb, s->next, st);
+        e = launch_step(s->h->prec, I.opk, I.mode, s->wide, I.nt, s->tab_dev, nullptr, I.nb, s->next, st);
         s->next += 1;
         s->written += 1;
     }
@@ -949,7 +963,7 @@ struct BatchLayout {
     std::vector<Plan> plans;
     std::vector<int> group_of;       // instance -> group
     std::vector<int> gkey;           // group -> kernel class
-    std::vector<int> gopk, gmode, gwide;
+    std::vector<int> gopk, gmode, gwide, gnt;
     std::vector<std::vector<int>> members;
     std::vector<uint32_t> gblocks;   // blocks per group launch
     size_t tab_off, map_off, inst_off, total;
@@ -967,7 +981,7 @@ bool batch_layout(kpm_ham *const *h, int32_t count, const int32_t *M, const int3
     for (int i = 0; i < count; ++i) {
         if (!h[i] || h[i]->prec != L.prec) return false;
         if (!make_plan(h[i], M[i], R[i], vec, L.plans[i])) return false;
-        const int key = kernel_key(h[i]->opk, L.plans[i].mode, L.plans[i].wide);
+        const int key = kernel_key(h[i]->opk, L.plans[i].mode, L.plans[i].wide, L.plans[i].nt);
         int g = -1;
         for (size_t k = 0; k < L.gkey.size(); ++k)
             if (L.gkey[k] == key) g = (int)k;
@@ -977,6 +991,7 @@ bool batch_layout(kpm_ham *const *h, int32_t count, const int32_t *M, const int3
             L.gopk.push_back(h[i]->opk);
             L.gmode.push_back(L.plans[i].mode);
             L.gwide.push_back(L.plans[i].wide);
+            L.gnt.push_back(L.plans[i].nt);
             L.members.emplace_back();
         }
         L.group_of[i] = g;
@@ -1071,8 +1086,8 @@ kpm_status kpm_moments_batched(kpm_ham *const *h, int32_t count, const int32_t *
         }
         for (size_t g = 0; g < L.gopk.size() && e == KPM_OK; ++g)
             if (L.gmode[g] != MODE_SMALL)
-                e = launch_step(L.prec, L.gopk[g], L.gmode[g], L.gwide[g], tab_dev + gfirst[g], map_dev + L.map_goff[g],
-                                L.gblocks[g], k, st);
+                e = launch_step(L.prec, L.gopk[g], L.gmode[g], L.gwide[g], L.gnt[g], tab_dev + gfirst[g],
+                                map_dev + L.map_goff[g], L.gblocks[g], k, st);
         written += 1;
     }
     if (e == KPM_OK) e = launch_reduce(tab_dev, count, reduced - 1, written - reduced, st);
@@ -1154,18 +1169,18 @@ kpm_status kpm_batch_advance(kpm_batch *b, int32_t steps, void *stream)
     if (act.empty() || steps == 0) return KPM_OK;
     std::vector<int> keys;
     for (kpm_solve *s : act) {
-        const int key = kernel_key(s->inst.opk, s->inst.mode, s->wide);
+        const int key = kernel_key(s->inst.opk, s->inst.mode, s->wide, s->inst.nt);
         if (std::find(keys.begin(), keys.end(), key) == keys.end()) keys.push_back(key);
     }
     std::vector<Inst> tab;
     std::vector<uint32_t> map;
-    struct Group { int opk, mode, wide; uint32_t first, count, blocks; size_t map_off; };
+    struct Group { int opk, mode, wide, nt; uint32_t first, count, blocks; size_t map_off; };
     std::vector<Group> groups;
     int32_t max_red = 0;
     for (int key : keys) {
-        Group g{0, 0, 0, (uint32_t)tab.size(), 0, 0, map.size()};
+        Group g{0, 0, 0, 0, (uint32_t)tab.size(), 0, 0, map.size()};
         for (kpm_solve *s : act) {
-            if (kernel_key(s->inst.opk, s->inst.mode, s->wide) != key) continue;
+            if (kernel_key(s->inst.opk, s->inst.mode, s->wide, s->inst.nt) != key) continue;
             Inst I = s->inst;
             I.step0 = s->next;
             I.block0 = g.blocks;
@@ -1179,6 +1194,7 @@ kpm_status kpm_batch_advance(kpm_batch *b, int32_t steps, void *stream)
             g.opk = I.opk;
             g.mode = I.mode;
             g.wide = s->wide;
+            g.nt = I.nt;
             tab.push_back(I);
         }
         groups.push_back(g);
@@ -1196,7 +1212,8 @@ kpm_status kpm_batch_advance(kpm_batch *b, int32_t steps, void *stream)
     for (int32_t k = 0; k < steps && e == KPM_OK; ++k)
         for (const Group &g : groups)
             if (e == KPM_OK)
-                e = launch_step(prec, g.opk, g.mode, g.wide, tab_dev + g.first, map_dev + g.map_off, g.blocks, k, st);
+                e = launch_step(prec, g.opk, g.mode, g.wide, g.nt, tab_dev + g.first, map_dev + g.map_off, g.blocks, k,
+                                st);
     if (e != KPM_OK) return e;
     for (kpm_solve *s : act) {
         s->reduced = s->written;
@@ -1205,6 +1222,71 @@ kpm_status kpm_batch_advance(kpm_batch *b, int32_t steps, void *stream)
         s->written += done;
     }
     return KPM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// captured graphs of a whole batched solve
+// ---------------------------------------------------------------------------
+struct kpm_graph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+kpm_status kpm_graph_capture_batched(kpm_ham *const *h, int32_t count, const int32_t *M, const int32_t *R,
+                                     int32_t vec, const uint64_t *seed, const uint64_t *instance, void *ws,
+                                     size_t ws_bytes, double *const *mu_dev, void *stream, kpm_graph **out)
+{
+    if (!out || !stream) return KPM_ERR_INVALID_ARG;      // capture needs a non-default stream
+    hipStream_t st = S(stream);
+    if (ensure_phase_table() != KPM_OK) return KPM_ERR_DEVICE;
+    // set LDS limits of the small-solve kernels outside the capture
+    for (int i = 0; i < count; ++i) {
+        Plan p;
+        if (h && h[i] && M && R && make_plan(h[i], M[i], R[i], vec, p) && p.mode == MODE_SMALL) {
+            small_fn f = h[i]->prec == KPM_F64 ? small_for<double>(h[i]->opk) : small_for<float>(h[i]->opk);
+            if (hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)small_lds_limit()) != hipSuccess)
+                return KPM_ERR_DEVICE;
+        }
+    }
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return KPM_ERR_DEVICE;
+    kpm_status e = kpm_moments_batched(h, count, M, R, vec, seed, instance, ws, ws_bytes, mu_dev, stream);
+    hipGraph_t g = nullptr;
+    hipError_t ce = hipStreamEndCapture(st, &g);
+    if (e != KPM_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return e;
+    }
+    if (ce != hipSuccess || !g) return KPM_ERR_DEVICE;
+    hipGraphExec_t x = nullptr;
+    if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return KPM_ERR_DEVICE;
+    }
+    kpm_graph *G = new (std::nothrow) kpm_graph();
+    if (!G) {
+        (void)hipGraphExecDestroy(x);
+        (void)hipGraphDestroy(g);
+        return KPM_ERR_OUT_OF_MEMORY;
+    }
+    G->graph = g;
+    G->exec = x;
+    *out = G;
+    return KPM_OK;
+}
+
+kpm_status kpm_graph_launch(kpm_graph *g, void *stream)
+{
+    if (!g) return KPM_ERR_INVALID_ARG;
+    return hipGraphLaunch(g->exec, S(stream)) == hipSuccess ? KPM_OK : KPM_ERR_DEVICE;
+}
+
+void kpm_graph_free(kpm_graph *g)
+{
+    if (!g) return;
+    (void)hipGraphExecDestroy(g->exec);
+    (void)hipGraphDestroy(g->graph);
+    delete g;
 }
 
 kpm_status kpm_dos(const double *mu_dev, int32_t M, int32_t jackson, int32_t K, double a, double b, double *omega_dev,
@@ -1260,6 +1342,10 @@ kpm_status kpm_set_launch(int32_t key, int32_t value)
         if (value != 0 && value != 1) return KPM_ERR_INVALID_ARG;
         g_small = value;
         return KPM_OK;
+    case KPM_LAUNCH_STREAMING:
+        if (value < 0 || value > 2) return KPM_ERR_INVALID_ARG;
+        g_streaming = value;
+        return KPM_OK;
     }
     return KPM_ERR_INVALID_ARG;
 }
@@ -1275,6 +1361,7 @@ kpm_status kpm_get_launch(int32_t key, int32_t *value)
     case KPM_LAUNCH_XCD_SPLIT: *value = g_xcd_split; return KPM_OK;
     case KPM_LAUNCH_ALTERNATE: *value = g_alternate; return KPM_OK;
     case KPM_LAUNCH_SMALL: *value = g_small; return KPM_OK;
+    case KPM_LAUNCH_STREAMING: *value = g_streaming; return KPM_OK;
     }
     return KPM_ERR_INVALID_ARG;
 }

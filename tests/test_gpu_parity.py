@@ -122,7 +122,7 @@ def test_launch_shape_does_not_change_fp64_result():
     for kw in [dict(max_blocks=2048), dict(max_blocks=8), dict(march_items=1), dict(march_items=100000),
                dict(march=0, elems_per_thread=4), dict(march=0, elems_per_thread=4, max_blocks=8),
                dict(march=0, elems_per_thread=1), dict(alternate=0), dict(xcd_split=1), dict(xcd_split=3),
-               dict(march_items=100000, xcd_split=2, alternate=1)]:
+               dict(march_items=100000, xcd_split=2, alternate=1), dict(streaming=0), dict(streaming=1)]:
         with kpm.launch_settings(**kw):
             outs.append(gu.gpu_moments(op, a, b, kpm.F64, 60, 5, wl.VEC_PHASE, seed=3))
     assert np.array_equal(outs[0], outs[1])              # same work items, different grid: bitwise
