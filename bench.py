@@ -32,7 +32,78 @@ WORKLOAD_TEXT = {
                "moments, R=32 random-phase vectors, complex64 recursion, FP64 moments, Jackson DoS on 2048 points",
     "config4": "2D square 2048^2 periodic lattice, Anderson disorder uniform[-1,1], M=4096 moments, R=64 +-1 "
                "vectors, FP32 recursion, FP64 moments, Jackson DoS on 8192 points",
+    "config3": "batch of 256 3D cubic spin-hopping lattices, L uniform in 16..48, base texture with 1-8 spins "
+               "re-drawn, M=512, R=16 random-phase vectors, complex64 recursion, FP64 moments, one captured graph",
 }
+
+
+def bench_batched(args, log_fn):
+    """Config 3: all 256 cubes solved together; a step = in-place operator preparation of every cube
+    plus one replay of the captured graph of the batched solve (init, 256 multi-instance recursion
+    launches, reductions, moments)."""
+    import torch
+    import paper_1105_5481_amd as kpm
+    from paper_1105_5481_amd import workloads as wl
+    cfg = wl.config3()
+    lats, M, R, vec, seed = cfg["lattices"], cfg["M"], cfg["R"], cfg["vec"], cfg["seed"]
+    hs, descs, keeps, scales = [], [], [], []
+    for lat in lats:
+        lo, hi = kpm.gershgorin(lat)
+        a, b = kpm.scale_from_bounds(lo, hi, 0.01)
+        hs.append(kpm.Hamiltonian(lat, a, b, kpm.F32))
+        d, keep = kpm._desc_for(lat, "cuda")
+        descs.append(d)
+        keeps.append(keep)
+        scales.append((a, b))
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        g = kpm.BatchedGraph(hs, M, R, vec, [seed] * len(hs), list(range(len(hs))), side)
+    L = kpm.lib()
+    sp = ctypes.c_void_p(side.cuda_stream)
+
+    def step():
+        for h, d, (a, b) in zip(hs, descs, scales):
+            kpm._check(L.kpm_update(h.handle, ctypes.byref(d), a, b, sp), "kpm_update")
+        g.launch()
+
+    for _ in range(args.warmup):
+        step()
+    side.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(side)
+    for _ in range(args.steps):
+        step()
+    e1.record(side)
+    side.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    gpu_ms = e0.elapsed_time(e1) / args.steps
+    N_tot = sum(l.N for l in lats)
+    updates = float(N_tot) * M * R
+    K = M // 2
+    bytes_step = sum(algorithmic_bytes_per_step(l.N, R, True, 4, False, 3) for l in lats)
+    # per recursion launch: the whole solve's time is charged to its K launches (conservative)
+    step_us = gpu_ms * 1e3 / K
+    achieved = bytes_step / (step_us * 1e-6) / 1e9
+    log_fn(f"bench: config3: {dt * 1e3:.2f} ms/step (GPU {gpu_ms:.2f} ms), {N_tot} sites")
+    mus = [m.cpu().numpy() for m in g.mus]
+    out = {
+        "metric": METRIC, "value": updates / dt, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+        "config": {"workload": WORKLOAD_TEXT["config3"], "instances": len(lats), "N_total": N_tot, "M": M, "R": R,
+                   "recursion": "complex64", "moments": "fp64"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_step_march<float, OP_SPIN3> (multi-instance)", "bytes_per_launch": bytes_step,
+                     "avg_launch_us": step_us, "note": "whole batched solve time divided by its 256 launches"},
+        "mu0_range": [min(m[0] for m in mus), max(m[0] for m in mus)],
+    }
+    g.free()
+    for h in hs:
+        h.free()
+    return out
+
 
 
 def log(msg):
@@ -166,11 +237,12 @@ def main():
     ap.add_argument("--xcd-split", type=int, default=-1, help="0 auto, 1 column tiles, 2 segments, 3 none")
     ap.add_argument("--alternate", type=int, default=-1)
     ap.add_argument("--streaming", type=int, default=-1)
+    ap.add_argument("--wave-mib", type=int, default=-1, help="batched solves: MiB of state per wave, 0 = one wave")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain 1 GiB device copy three times (counter calibration under rocprofv3)")
     ap.add_argument("--pmc-summary", metavar="DIR",
                     help="print per-kernel averages of rocprofv3 --pmc CSV files found under DIR and exit")
-    ap.add_argument("--workload", default="config2", choices=["config2", "config4"],
+    ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config4"],
                     help="config2 (the measured workload) or config4 (2D 2048^2, R=64, real FP32) for exploration")
     args = ap.parse_args()
 
@@ -202,10 +274,14 @@ def main():
                    march=None if args.march < 0 else args.march, march_items=args.march_items or None,
                    xcd_split=None if args.xcd_split < 0 else args.xcd_split,
                    alternate=None if args.alternate < 0 else args.alternate,
-                   streaming=None if args.streaming < 0 else args.streaming)
+                   streaming=None if args.streaming < 0 else args.streaming,
+                   wave_mib=None if args.wave_mib < 0 else args.wave_mib)
     dev = "cuda"
     stream = torch.cuda.current_stream()
 
+    if args.workload == "config3":
+        print(json.dumps(bench_batched(args, log)), flush=True)
+        return
     cfg = wl.config2() if args.workload == "config2" else wl.config4()
     lat, M, R, vec, seed = cfg["lattice"], cfg["M"], cfg["R"], cfg["vec"], cfg["seed"]
     cplx = lat.hop == wl.HOP_SPIN or vec == wl.VEC_PHASE

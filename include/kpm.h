@@ -252,6 +252,11 @@ kpm_status kpm_start_vectors(int32_t vec, int32_t complex_layout, uint64_t seed,
  *                                non-temporal hints, 0 = cached, 2 (default) = cached when
  *                                vectors and operator take at most 192 MiB (they then stay
  *                                in the 256 MiB Infinity Cache between steps), else 1
+ *   KPM_LAUNCH_WAVE_MIB          kpm_moments_batched: instances run in waves, each wave
+ *                                taking the next instances (in argument order) while their
+ *                                vectors and operators total at most this many MiB (default
+ *                                192, so a wave stays in the Infinity Cache); a wave runs all
+ *                                its recursion steps before the next starts.  0 = one wave
  * The partial sums of the dot products are formed per work item, so the
  * moments do not depend on the grid (MAX_BLOCKS) nor on the batch an instance
  * runs in; the other keys change the work items and with them the order in
@@ -265,7 +270,8 @@ typedef enum {
     KPM_LAUNCH_XCD_SPLIT = 4,
     KPM_LAUNCH_ALTERNATE = 5,
     KPM_LAUNCH_SMALL = 6,
-    KPM_LAUNCH_STREAMING = 7
+    KPM_LAUNCH_STREAMING = 7,
+    KPM_LAUNCH_WAVE_MIB = 8
 } kpm_launch_key;
 kpm_status kpm_set_launch(int32_t key, int32_t value);
 kpm_status kpm_get_launch(int32_t key, int32_t *value);

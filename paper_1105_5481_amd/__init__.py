@@ -74,6 +74,7 @@ def lib():
         "kpm_set_launch": (i32, [i32, i32]),
         "kpm_get_launch": (i32, [i32, P]),
         "kpm_selftest_fastdiv": (i32, [ctypes.c_uint32, P, i32]),
+        "kpm_selftest_placement": (ctypes.c_int64, [P, P, i32, P, P, P, ctypes.c_int64]),
         "kpm_solve_remaining": (i32, [P, P]),
         "kpm_request_bytes": (sz, [pdesc, i32, i32, i32, i32]),
         "kpm_ham_bytes": (sz, [P]),
@@ -440,7 +441,7 @@ def start_vectors(vec: int, complex_layout: bool, seed: int, instance: int, N: i
 LAUNCH_ELEMS_PER_THREAD, LAUNCH_MAX_BLOCKS, LAUNCH_MARCH, LAUNCH_MARCH_ITEMS, LAUNCH_XCD_SPLIT, LAUNCH_ALTERNATE, \
     LAUNCH_SMALL, LAUNCH_STREAMING = range(8)
 _LAUNCH_KEYS = {"elems_per_thread": 0, "max_blocks": 1, "march": 2, "march_items": 3, "xcd_split": 4, "alternate": 5,
-                "small": 6, "streaming": 7}
+                "small": 6, "streaming": 7, "wave_mib": 8}
 
 
 def set_launch(**kw):

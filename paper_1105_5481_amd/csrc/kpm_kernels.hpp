@@ -44,6 +44,7 @@ enum { VEC_RADEMACHER = 0, VEC_PHASE = 1, VEC_UNIT = 2 };
 enum { MODE_FLAT = 0, MODE_MARCH = 1, MODE_SMALL = 2 };
 constexpr int BLOCK = 256;
 constexpr uint32_t XCD_MIN_ITEMS = 64;   // below this an instance's items are not split per XCD
+constexpr uint32_t NO_INSTANCE = 0xffffffffu;   // block-map entry of an idle block
 
 // One solve inside a launch (device-resident table entry).
 struct Inst {
@@ -60,7 +61,8 @@ struct Inst {
     uint32_t nel;      // N * C
     uint32_t tiles;    // work items per step (= partials per step)
     uint32_t nb;       // blocks given to this instance (multiple of 8)
-    uint32_t block0;   // first block of this instance in the grid (multiple of 8)
+    uint32_t block0;   // first block of this instance in the grid
+    uint32_t bstride;  // its blocks are block0, block0 + bstride, ... (1, or 8 to keep them on one XCD)
     int32_t tpt;       // flat: chunks per thread per tile
     uint32_t P, Lm, S, nct, nseg;  // march: plane size, march extent, segment, column tiles, segments
     int32_t cplx;      // data stored as interleaved complex
@@ -274,7 +276,7 @@ struct ItemRange {
 };
 __device__ __forceinline__ ItemRange item_range(const Inst &I, uint32_t units, uint32_t segs)
 {
-    const uint32_t bl = blockIdx.x - I.block0;
+    const uint32_t bl = (blockIdx.x - I.block0) / I.bstride;
     ItemRange r;
     r.ub = 0;
     r.nu = units;
@@ -386,10 +388,11 @@ __device__ __forceinline__ typename V16<S>::T start_chunk(const Inst &I, uint32_
 // r_0 into buf0 and the partials of <r_0|r_0>, over the same work items as the
 // recursion step of the instance's mode.
 template <typename S, bool WIDE>
-__global__ __launch_bounds__(BLOCK) void k_init(const Inst *__restrict__ tab, const uint32_t *__restrict__ map8)
+__global__ __launch_bounds__(BLOCK) void k_init(const Inst *__restrict__ tab, const uint32_t *__restrict__ bmap)
 {
     typedef Mem<S, WIDE> G;
-    const uint32_t h = map8 ? map8[blockIdx.x >> 3] : 0u;
+    const uint32_t h = bmap ? bmap[blockIdx.x] : 0u;
+    if (h == NO_INSTANCE) return;
     const Inst I = tab[h];
     if (I.step0 != 0) return;
     double *part = I.partial;   // slot 0
@@ -486,7 +489,7 @@ __device__ __forceinline__ typename V16<S>::T apply_cplx(bool hd, S d, typename 
 // ---------------------------------------------------------------------------
 template <typename S, int OPK, bool WIDE, bool NT>
 __global__ __launch_bounds__(BLOCK) void k_step_march(const Inst *__restrict__ tab,
-                                                      const uint32_t *__restrict__ map8, int32_t k)
+                                                      const uint32_t *__restrict__ bmap, int32_t k)
 {
     typedef typename V16<S>::T T;
     typedef Mem<S, WIDE> G;
@@ -495,7 +498,8 @@ __global__ __launch_bounds__(BLOCK) void k_step_march(const Inst *__restrict__ t
     constexpr bool SPIN = (OPK == OP_SPIN2 || OPK == OP_SPIN3);
     constexpr int DIM = D3 ? 3 : 2;
     constexpr int NS = 2 * DIM;
-    const uint32_t h = map8 ? map8[blockIdx.x >> 3] : 0u;
+    const uint32_t h = bmap ? bmap[blockIdx.x] : 0u;
+    if (h == NO_INSTANCE) return;
     const Inst I = tab[h];
     const int32_t n = I.step0 + k;
     if (n < 0 || n >= I.K) return;
@@ -690,10 +694,11 @@ __device__ __forceinline__ void flat_elem(const Inst &I, uint32_t e, const void 
 }
 
 template <typename S, int OPK, bool WIDE>
-__global__ __launch_bounds__(BLOCK) void k_step_flat(const Inst *__restrict__ tab, const uint32_t *__restrict__ map8,
+__global__ __launch_bounds__(BLOCK) void k_step_flat(const Inst *__restrict__ tab, const uint32_t *__restrict__ bmap,
                                                      int32_t k)
 {
-    const uint32_t h = map8 ? map8[blockIdx.x >> 3] : 0u;
+    const uint32_t h = bmap ? bmap[blockIdx.x] : 0u;
+    if (h == NO_INSTANCE) return;
     const Inst I = tab[h];
     const int32_t n = I.step0 + k;
     if (n < 0 || n >= I.K) return;

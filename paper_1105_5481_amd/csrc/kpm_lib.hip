@@ -25,6 +25,7 @@ int g_xcd_split = 0;                    // 0 automatic, 1 by column tiles, 2 by 
 int g_alternate = 1;                    // march: odd segments walk downwards
 int g_small = 1;                        // solves whose two vector blocks fit in LDS run in one workgroup
 int g_streaming = 2;                    // march: 0 cached, 1 non-temporal access of r_{n-1}/r_{n+1}, 2 by size
+int g_wave_mib = 192;                   // batched solves: vectors + operators per wave (MiB), 0 = one wave
 constexpr uint64_t CACHE_RESIDENT_BYTES = 192ull << 20;   // below this the state stays in the 256 MiB Infinity Cache
 
 // Dynamic LDS one workgroup may use for the small-solve path (0 if no device).
@@ -417,6 +418,7 @@ struct kpm_solve {
     int32_t next;      // next recursion step n to run
     int32_t written;   // dots indices [0, written) have partials
     int32_t reduced;   // dots indices [0, reduced) are reduced
+    uint64_t state;    // bytes the recursion touches per step (vectors + operator)
 };
 
 namespace {
@@ -429,7 +431,17 @@ struct Plan {
     int32_t K, P_slots, tpt;
     size_t esz;
     size_t part_bytes, dots_bytes, buf_bytes;
+    uint64_t state;   // bytes the recursion touches per step (vectors + operator)
 };
+
+// Store kind for r_{n+1}: it is read again as r_n by the next step, so keep it
+// cached when everything the recursion touches per step (all instances of a
+// batch together) fits the Infinity Cache, and stream it past the caches
+// otherwise.
+int stream_choice(uint64_t state_bytes)
+{
+    return g_streaming == 2 ? (state_bytes > CACHE_RESIDENT_BYTES ? 1 : 0) : g_streaming;
+}
 
 bool make_plan(const kpm_ham *h, int32_t M, int32_t R, int32_t vec, Plan &p)
 {
@@ -493,8 +505,8 @@ bool make_plan(const kpm_ham *h, int32_t M, int32_t R, int32_t vec, Plan &p)
     }
     // r_{n+1} is read again as r_n by the next step: keep it cached when the
     // whole state fits the Infinity Cache, stream it otherwise
-    const uint64_t state = 2ull * p.buf_bytes + (uint64_t)h->N * (h->dim ? (1 + 2 * h->dim) : 1) * p.esz;
-    p.nt = g_streaming == 2 ? (state > CACHE_RESIDENT_BYTES ? 1 : 0) : g_streaming;
+    p.state = 2ull * p.buf_bytes + (uint64_t)h->N * (h->dim ? (1 + 2 * h->dim) : 1) * p.esz;
+    p.nt = stream_choice(p.state);
     return true;
 }
 
@@ -519,6 +531,7 @@ void fill_inst(const kpm_ham *h, const Plan &p, int32_t M, int32_t R, int32_t ve
     I.tiles = p.tiles;
     I.nb = p.nb;
     I.block0 = 0;
+    I.bstride = 1;
     I.tpt = p.tpt;
     I.mode = p.mode;
     I.xcd = p.xcd;
@@ -552,15 +565,15 @@ void fill_inst(const kpm_ham *h, const Plan &p, int32_t M, int32_t R, int32_t ve
     I.mu = nullptr;
 }
 
-kpm_status launch_init(int prec, int wide, const Inst *tab, const uint32_t *map8, uint32_t blocks, hipStream_t st)
+kpm_status launch_init(int prec, int wide, const Inst *tab, const uint32_t *bmap, uint32_t blocks, hipStream_t st)
 {
-    hipLaunchKernelGGL(get_init(prec, wide), dim3(blocks), dim3(BLOCK), 0, st, tab, map8);
+    hipLaunchKernelGGL(get_init(prec, wide), dim3(blocks), dim3(BLOCK), 0, st, tab, bmap);
     return check_launch();
 }
-kpm_status launch_step(int prec, int opk, int mode, int wide, int nt, const Inst *tab, const uint32_t *map8,
+kpm_status launch_step(int prec, int opk, int mode, int wide, int nt, const Inst *tab, const uint32_t *bmap,
                        uint32_t blocks, int32_t k, hipStream_t st)
 {
-    hipLaunchKernelGGL(get_step(prec, opk, mode, wide, nt), dim3(blocks), dim3(BLOCK), 0, st, tab, map8, k);
+    hipLaunchKernelGGL(get_step(prec, opk, mode, wide, nt), dim3(blocks), dim3(BLOCK), 0, st, tab, bmap, k);
     return check_launch();
 }
 typedef void (*small_fn)(const Inst *);
@@ -864,6 +877,7 @@ kpm_status kpm_solve_begin(kpm_ham *h, int32_t M, int32_t R, int32_t vec, uint64
     if (!s) return KPM_ERR_OUT_OF_MEMORY;
     hipStream_t st = S(stream);
     s->h = h;
+    s->state = p.state;
     s->ws = (char *)ws;
     s->tab_dev = (Inst *)ws;
     fill_inst(h, p, M, R, vec, seed, instance, s->ws + align256(sizeof(Inst)), s->inst);
@@ -959,57 +973,148 @@ kpm_status kpm_moments(kpm_ham *h, int32_t M, int32_t R, int32_t vec, uint64_t s
 // batched solves
 // ---------------------------------------------------------------------------
 namespace {
+// Block placement of one launch group (instances of one kernel class, in table
+// order).  Instances whose work is split per XCD take a contiguous,
+// 8-aligned block range.  The others are packed in octets of similar size:
+// instance k of an octet owns blocks region + k + 8 j (stride 8), so all its
+// blocks run on one XCD and its in-plane neighbours stay in that XCD's L2.
+// Writes block0/bstride into the instances and the per-block map (instance
+// index within the group, NO_INSTANCE for idle blocks); returns the grid size.
+uint32_t place_blocks(std::vector<Inst> &ins, std::vector<uint32_t> &map)
+{
+    std::vector<uint32_t> big, small;
+    for (uint32_t r = 0; r < ins.size(); ++r) (ins[r].xcd ? big : small).push_back(r);
+    std::sort(small.begin(), small.end(), [&](uint32_t a, uint32_t b) { return ins[a].nb > ins[b].nb; });
+    uint32_t blocks = 0;
+    for (uint32_t r : big) {
+        ins[r].block0 = blocks;
+        ins[r].bstride = 1;
+        for (uint32_t j = 0; j < ins[r].nb; ++j) map.push_back(r);
+        blocks += ins[r].nb;
+    }
+    for (size_t o = 0; o < small.size(); o += 8) {
+        const size_t n = std::min<size_t>(8, small.size() - o);
+        uint32_t per = 0;
+        for (size_t k = 0; k < n; ++k) per = std::max(per, ins[small[o + k]].nb);
+        const size_t base = map.size();
+        map.resize(base + 8 * (size_t)per, NO_INSTANCE);
+        for (size_t k = 0; k < n; ++k) {
+            Inst &I = ins[small[o + k]];
+            I.block0 = blocks + (uint32_t)k;
+            I.bstride = 8;
+            for (uint32_t j = 0; j < I.nb; ++j) map[base + k + 8 * (size_t)j] = small[o + k];
+        }
+        blocks += 8 * per;
+    }
+    return blocks;
+}
+}  // namespace
+namespace {
+// One multi-instance launch: the instances of one kernel class, contiguous in
+// the table, with their block map.
+struct BatchGroup {
+    int opk, mode, wide, nt;
+    uint32_t first, count;   // table range
+    uint32_t blocks;         // grid size
+    size_t map_off;          // offset into the block map (words)
+    size_t lds;              // single-workgroup solves: dynamic LDS bytes
+};
+// Instances whose recursions run together, step by step, before the next wave
+// starts.  A wave's vectors and operators are sized to stay in the Infinity
+// Cache between steps.
+struct BatchWave {
+    uint32_t first, count;   // table range
+    int32_t Kmax;
+    std::vector<BatchGroup> groups;
+};
 struct BatchLayout {
     std::vector<Plan> plans;
-    std::vector<int> group_of;       // instance -> group
-    std::vector<int> gkey;           // group -> kernel class
-    std::vector<int> gopk, gmode, gwide, gnt;
-    std::vector<std::vector<int>> members;
-    std::vector<uint32_t> gblocks;   // blocks per group launch
-    size_t tab_off, map_off, inst_off, total;
-    std::vector<size_t> map_goff;    // per group offset into the map region (in uint32)
-    std::vector<size_t> region_off;  // per instance
+    std::vector<int> order;           // table index -> instance
+    std::vector<BatchGroup> small;    // single-workgroup solves, one launch per kernel class
+    std::vector<BatchWave> waves;
+    size_t tab_off, map_off, inst_off, total, map_words;
+    std::vector<size_t> region_off;   // per instance
     int prec;
 };
+
+// Appends the groups of instances `ids` (one per kernel class, in order of
+// first appearance) to `groups`, their instances to L.order, and sizes their
+// block maps.
+void add_groups(kpm_ham *const *h, const std::vector<int> &ids, BatchLayout &L, std::vector<BatchGroup> &groups)
+{
+    std::vector<int> keys;
+    for (int i : ids) {
+        const int key = kernel_key(h[i]->opk, L.plans[i].mode, L.plans[i].wide, L.plans[i].nt);
+        if (std::find(keys.begin(), keys.end(), key) == keys.end()) keys.push_back(key);
+    }
+    for (int key : keys) {
+        BatchGroup g{0, 0, 0, 0, (uint32_t)L.order.size(), 0, 0, L.map_words, 0};
+        std::vector<Inst> ins;
+        for (int i : ids) {
+            const Plan &p = L.plans[i];
+            if (kernel_key(h[i]->opk, p.mode, p.wide, p.nt) != key) continue;
+            g.opk = h[i]->opk;
+            g.mode = p.mode;
+            g.wide = p.wide;
+            g.nt = p.nt;
+            g.lds = std::max(g.lds, 2 * (size_t)p.nel * 16);
+            Inst I;
+            std::memset(&I, 0, sizeof(I));
+            I.nb = p.nb;
+            I.xcd = p.xcd;
+            ins.push_back(I);
+            L.order.push_back(i);
+        }
+        g.count = (uint32_t)ins.size();
+        if (g.mode != MODE_SMALL) {
+            std::vector<uint32_t> m;
+            g.blocks = place_blocks(ins, m);
+            L.map_words += m.size();
+        }
+        groups.push_back(g);
+    }
+}
 
 bool batch_layout(kpm_ham *const *h, int32_t count, const int32_t *M, const int32_t *R, int32_t vec, BatchLayout &L)
 {
     if (!h || count < 1 || count > 65535 || !M || !R) return false;
     L.plans.resize(count);
-    L.group_of.assign(count, -1);
     L.prec = h[0] ? h[0]->prec : -1;
+    L.map_words = 0;
+    std::vector<int> small;
+    std::vector<std::vector<int>> waves;
+    const uint64_t wave_bytes = (uint64_t)g_wave_mib << 20;
+    uint64_t wave_state = 0;
     for (int i = 0; i < count; ++i) {
         if (!h[i] || h[i]->prec != L.prec) return false;
         if (!make_plan(h[i], M[i], R[i], vec, L.plans[i])) return false;
-        const int key = kernel_key(h[i]->opk, L.plans[i].mode, L.plans[i].wide, L.plans[i].nt);
-        int g = -1;
-        for (size_t k = 0; k < L.gkey.size(); ++k)
-            if (L.gkey[k] == key) g = (int)k;
-        if (g < 0) {
-            g = (int)L.gkey.size();
-            L.gkey.push_back(key);
-            L.gopk.push_back(h[i]->opk);
-            L.gmode.push_back(L.plans[i].mode);
-            L.gwide.push_back(L.plans[i].wide);
-            L.gnt.push_back(L.plans[i].nt);
-            L.members.emplace_back();
+        if (L.plans[i].mode == MODE_SMALL) {
+            small.push_back(i);
+            continue;
         }
-        L.group_of[i] = g;
-        L.members[g].push_back(i);
+        if (waves.empty() || (wave_bytes && wave_state + L.plans[i].state > wave_bytes)) {
+            waves.emplace_back();
+            wave_state = 0;
+        }
+        waves.back().push_back(i);
+        wave_state += L.plans[i].state;
     }
-    L.gblocks.assign(L.gopk.size(), 0);
-    L.map_goff.assign(L.gopk.size(), 0);
-    size_t map_words = 0;
-    for (size_t g = 0; g < L.gopk.size(); ++g) {
-        uint32_t b = 0;
-        for (int i : L.members[g]) b += L.plans[i].nb;
-        L.gblocks[g] = b;
-        L.map_goff[g] = map_words;
-        map_words += b / 8;
+    add_groups(h, small, L, L.small);
+    for (const std::vector<int> &w : waves) {
+        // the instances of a wave share the caches
+        uint64_t state = 0;
+        for (int i : w) state += L.plans[i].state;
+        BatchWave bw{(uint32_t)L.order.size(), (uint32_t)w.size(), 0, {}};
+        for (int i : w) {
+            L.plans[i].nt = stream_choice(state);
+            bw.Kmax = std::max(bw.Kmax, L.plans[i].K);
+        }
+        add_groups(h, w, L, bw.groups);
+        L.waves.push_back(std::move(bw));
     }
     L.tab_off = 0;
     L.map_off = align256((size_t)count * sizeof(Inst));
-    L.inst_off = L.map_off + align256(map_words * 4 + 4);
+    L.inst_off = L.map_off + align256(L.map_words * 4 + 4);
     L.region_off.resize(count);
     size_t off = L.inst_off;
     for (int i = 0; i < count; ++i) {
@@ -1041,56 +1146,47 @@ kpm_status kpm_moments_batched(kpm_ham *const *h, int32_t count, const int32_t *
     hipStream_t st = S(stream);
     char *base = (char *)ws;
     std::vector<Inst> tab(count);
-    std::vector<uint32_t> map;
-    std::vector<uint32_t> gfirst(L.gopk.size());  // first table index of each group
-    // Instances are laid out in the table group by group so each group's launch
-    // sees a contiguous table and its own block map.
-    std::vector<int> order;
-    for (size_t g = 0; g < L.gopk.size(); ++g) {
-        gfirst[g] = (uint32_t)order.size();
-        for (int i : L.members[g]) order.push_back(i);
+    int32_t Mmax = 0;
+    for (int t = 0; t < count; ++t) {
+        const int i = L.order[t];
+        fill_inst(h[i], L.plans[i], M[i], R[i], vec, seed[i], instance[i], base + L.region_off[i], tab[t]);
+        tab[t].mu = mu_dev[i];
+        Mmax = std::max(Mmax, M[i]);
     }
-    int32_t Kmax = 0, Mmax = 0;
-    for (size_t g = 0; g < L.gopk.size(); ++g) {
-        uint32_t blk = 0;
-        for (size_t r = 0; r < L.members[g].size(); ++r) {
-            const int i = L.members[g][r];
-            const uint32_t ti = gfirst[g] + (uint32_t)r;
-            fill_inst(h[i], L.plans[i], M[i], R[i], vec, seed[i], instance[i], base + L.region_off[i], tab[ti]);
-            tab[ti].block0 = blk;
-            tab[ti].mu = mu_dev[i];
-            for (uint32_t b = 0; b < L.plans[i].nb / 8; ++b) map.push_back(r);
-            blk += L.plans[i].nb;
-            Kmax = std::max(Kmax, L.plans[i].K);
-            Mmax = std::max(Mmax, M[i]);
-        }
+    // block maps, with the placement batch_layout sized them for
+    std::vector<uint32_t> map;
+    std::vector<const BatchGroup *> all;
+    for (const BatchWave &w : L.waves)
+        for (const BatchGroup &g : w.groups) all.push_back(&g);
+    for (const BatchGroup *g : all) {
+        std::vector<Inst> ins(tab.begin() + g->first, tab.begin() + g->first + g->count);
+        if (map.size() != g->map_off || place_blocks(ins, map) != g->blocks) return KPM_ERR_INVALID_ARG;
+        std::copy(ins.begin(), ins.end(), tab.begin() + g->first);
     }
     Inst *tab_dev = (Inst *)(base + L.tab_off);
     uint32_t *map_dev = (uint32_t *)(base + L.map_off);
     kpm_status e = upload(tab_dev, tab.data(), tab.size() * sizeof(Inst), st);
     if (e == KPM_OK && !map.empty()) e = upload(map_dev, map.data(), map.size() * 4, st);
-    for (size_t g = 0; g < L.gopk.size() && e == KPM_OK; ++g) {
-        if (L.gmode[g] == MODE_SMALL) {
-            size_t lds = 0;
-            for (int i : L.members[g]) lds = std::max(lds, 2 * (size_t)L.plans[i].nel * 16);
-            e = launch_small(L.prec, L.gopk[g], tab_dev + gfirst[g], (uint32_t)L.members[g].size(), lds, st);
-        } else {
-            e = launch_init(L.prec, L.gwide[g], tab_dev + gfirst[g], map_dev + L.map_goff[g], L.gblocks[g], st);
+    for (const BatchGroup &g : L.small)
+        if (e == KPM_OK) e = launch_small(L.prec, g.opk, tab_dev + g.first, g.count, g.lds, st);
+    for (const BatchWave &w : L.waves) {
+        for (const BatchGroup &g : w.groups)
+            if (e == KPM_OK) e = launch_init(L.prec, g.wide, tab_dev + g.first, map_dev + g.map_off, g.blocks, st);
+        Inst *wt = tab_dev + w.first;
+        int32_t written = 1, reduced = 0;  // dots indices, in lockstep for every instance of the wave
+        for (int32_t k = 0; k < w.Kmax && e == KPM_OK; ++k) {
+            if (written - reduced >= PSLOTS_MAX) {
+                e = launch_reduce(wt, (int32_t)w.count, reduced - 1, written - reduced, st);
+                reduced = written;
+            }
+            for (const BatchGroup &g : w.groups)
+                if (e == KPM_OK)
+                    e = launch_step(L.prec, g.opk, g.mode, g.wide, g.nt, tab_dev + g.first, map_dev + g.map_off,
+                                    g.blocks, k, st);
+            written += 1;
         }
+        if (e == KPM_OK) e = launch_reduce(wt, (int32_t)w.count, reduced - 1, written - reduced, st);
     }
-    int32_t written = 1, reduced = 0;  // dots indices, in lockstep for every instance
-    for (int32_t k = 0; k < Kmax && e == KPM_OK; ++k) {
-        if (written - reduced >= PSLOTS_MAX) {
-            e = launch_reduce(tab_dev, count, reduced - 1, written - reduced, st);
-            reduced = written;
-        }
-        for (size_t g = 0; g < L.gopk.size() && e == KPM_OK; ++g)
-            if (L.gmode[g] != MODE_SMALL)
-                e = launch_step(L.prec, L.gopk[g], L.gmode[g], L.gwide[g], L.gnt[g], tab_dev + gfirst[g],
-                                map_dev + L.map_goff[g], L.gblocks[g], k, st);
-        written += 1;
-    }
-    if (e == KPM_OK) e = launch_reduce(tab_dev, count, reduced - 1, written - reduced, st);
     if (e == KPM_OK) e = launch_moments(tab_dev, count, Mmax, st);
     return e;
 }
@@ -1111,7 +1207,7 @@ kpm_status kpm_batch_create(int32_t capacity, kpm_batch **out)
     kpm_batch *b = new (std::nothrow) kpm_batch();
     if (!b) return KPM_ERR_OUT_OF_MEMORY;
     b->capacity = capacity;
-    b->map_words = (size_t)capacity * (size_t)std::max(g_max_blocks, 8192) / 8 + 8;
+    b->map_words = (size_t)(std::min(capacity, 64) + 8) * 2048;
     const size_t bytes = align256((size_t)capacity * sizeof(Inst)) + b->map_words * 4;
     if (hipMalloc((void **)&b->mem, bytes) != hipSuccess) {
         delete b;
@@ -1120,6 +1216,27 @@ kpm_status kpm_batch_create(int32_t capacity, kpm_batch **out)
     *out = b;
     return KPM_OK;
 }
+
+namespace {
+// Grow the batch's table + block-map memory to hold `words` map entries.  The
+// old memory may still be read by launches in flight on `st`, so wait for them.
+kpm_status batch_reserve(kpm_batch *b, size_t words, hipStream_t st)
+{
+    if (words <= b->map_words) return KPM_OK;
+    if (hipStreamSynchronize(st) != hipSuccess) return KPM_ERR_DEVICE;
+    const size_t nw = std::max(words, 2 * b->map_words);
+    char *mem = nullptr;
+    if (hipMalloc((void **)&mem, align256((size_t)b->capacity * sizeof(Inst)) + nw * 4) != hipSuccess)
+        return KPM_ERR_OUT_OF_MEMORY;
+    if (hipFree(b->mem) != hipSuccess) {
+        (void)hipFree(mem);
+        return KPM_ERR_DEVICE;
+    }
+    b->mem = mem;
+    b->map_words = nw;
+    return KPM_OK;
+}
+}  // namespace
 
 void kpm_batch_free(kpm_batch *b)
 {
@@ -1167,9 +1284,13 @@ kpm_status kpm_batch_advance(kpm_batch *b, int32_t steps, void *stream)
     for (kpm_solve *s : b->members)
         if (s->inst.mode != MODE_SMALL && (s->next < s->inst.K || s->written > s->reduced)) act.push_back(s);
     if (act.empty() || steps == 0) return KPM_OK;
+    // the members of one launch share the caches
+    uint64_t state = 0;
+    for (kpm_solve *s : act) state += s->state;
+    const int nt = stream_choice(state);
     std::vector<int> keys;
     for (kpm_solve *s : act) {
-        const int key = kernel_key(s->inst.opk, s->inst.mode, s->wide, s->inst.nt);
+        const int key = kernel_key(s->inst.opk, s->inst.mode, s->wide, nt);
         if (std::find(keys.begin(), keys.end(), key) == keys.end()) keys.push_back(key);
     }
     std::vector<Inst> tab;
@@ -1179,27 +1300,27 @@ kpm_status kpm_batch_advance(kpm_batch *b, int32_t steps, void *stream)
     int32_t max_red = 0;
     for (int key : keys) {
         Group g{0, 0, 0, 0, (uint32_t)tab.size(), 0, 0, map.size()};
+        std::vector<Inst> ins;
         for (kpm_solve *s : act) {
-            if (kernel_key(s->inst.opk, s->inst.mode, s->wide, s->inst.nt) != key) continue;
+            if (kernel_key(s->inst.opk, s->inst.mode, s->wide, nt) != key) continue;
             Inst I = s->inst;
+            I.nt = nt;
             I.step0 = s->next;
-            I.block0 = g.blocks;
             I.red_lo = s->reduced;
             I.red_n = s->written - s->reduced;
             max_red = std::max(max_red, I.red_n);
-            const uint32_t r = g.count;
-            for (uint32_t k = 0; k < I.nb / 8; ++k) map.push_back(r);
-            g.blocks += I.nb;
-            g.count += 1;
             g.opk = I.opk;
             g.mode = I.mode;
             g.wide = s->wide;
             g.nt = I.nt;
-            tab.push_back(I);
+            ins.push_back(I);
         }
+        g.count = (uint32_t)ins.size();
+        g.blocks = place_blocks(ins, map);
+        tab.insert(tab.end(), ins.begin(), ins.end());
         groups.push_back(g);
     }
-    if (map.size() > b->map_words) return KPM_ERR_UNSUPPORTED;
+    if (kpm_status r = batch_reserve(b, map.size(), st)) return r;
     Inst *tab_dev = (Inst *)b->mem;
     uint32_t *map_dev = (uint32_t *)(b->mem + align256((size_t)b->capacity * sizeof(Inst)));
     kpm_status e = upload(tab_dev, tab.data(), tab.size() * sizeof(Inst), st);
@@ -1346,6 +1467,10 @@ kpm_status kpm_set_launch(int32_t key, int32_t value)
         if (value < 0 || value > 2) return KPM_ERR_INVALID_ARG;
         g_streaming = value;
         return KPM_OK;
+    case KPM_LAUNCH_WAVE_MIB:
+        if (value < 0 || value > (1 << 22)) return KPM_ERR_INVALID_ARG;
+        g_wave_mib = value;
+        return KPM_OK;
     }
     return KPM_ERR_INVALID_ARG;
 }
@@ -1362,6 +1487,7 @@ kpm_status kpm_get_launch(int32_t key, int32_t *value)
     case KPM_LAUNCH_ALTERNATE: *value = g_alternate; return KPM_OK;
     case KPM_LAUNCH_SMALL: *value = g_small; return KPM_OK;
     case KPM_LAUNCH_STREAMING: *value = g_streaming; return KPM_OK;
+    case KPM_LAUNCH_WAVE_MIB: *value = g_wave_mib; return KPM_OK;
     }
     return KPM_ERR_INVALID_ARG;
 }
@@ -1374,6 +1500,31 @@ int32_t kpm_selftest_fastdiv(uint32_t d, const uint32_t *n, int32_t count)
     for (int32_t k = 0; k < count; ++k)
         if (fdiv(n[k], f) != n[k] / d) return k + 1;
     return 0;
+}
+
+// Host check of the block placement of one launch group: nb[i] blocks and the
+// XCD split flag of instance i.  Writes block0/bstride per instance and the
+// per-block map (up to map_cap entries); returns the grid size, or -1 if the
+// map does not fit.
+int64_t kpm_selftest_placement(const uint32_t *nb, const int32_t *xcd, int32_t count, uint32_t *block0,
+                               uint32_t *bstride, uint32_t *map_out, int64_t map_cap)
+{
+    if (!nb || !xcd || count < 1 || !block0 || !bstride || !map_out) return -1;
+    std::vector<Inst> ins(count);
+    for (int32_t i = 0; i < count; ++i) {
+        std::memset(&ins[i], 0, sizeof(Inst));
+        ins[i].nb = nb[i];
+        ins[i].xcd = xcd[i];
+    }
+    std::vector<uint32_t> map;
+    const uint32_t blocks = place_blocks(ins, map);
+    if ((int64_t)map.size() > map_cap || map.size() != blocks) return -1;
+    for (int32_t i = 0; i < count; ++i) {
+        block0[i] = ins[i].block0;
+        bstride[i] = ins[i].bstride;
+    }
+    std::copy(map.begin(), map.end(), map_out);
+    return blocks;
 }
 
 }  // extern "C"

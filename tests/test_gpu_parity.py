@@ -172,6 +172,30 @@ def test_batched_equals_solo_bitwise(prec):
         h.free()
 
 
+@pytest.mark.parametrize("prec", [kpm.F64, kpm.F32])
+def test_batched_waves_bitwise(prec):
+    """Batched solves split into cache-sized waves (1 MiB forces several waves, 0 one wave) give
+    the solo moments bit for bit, with single-workgroup, march and CSR instances mixed."""
+    ops = [wl.spin_cubic_lattice(5, seed=70), wl.spin_cubic_lattice(12, seed=71), wl.spin_cubic_lattice(17, seed=72),
+           wl.square_lattice(70, W=1.0, seed=73), wl.lattice_to_csr(wl.square_lattice(30, W=1.0, seed=74)),
+           wl.cubic_lattice(16, W=2.0, seed=75)]
+    hs = []
+    for op in ops:
+        lo, hi = gu.oracle_bounds(op)
+        a, b = oracle.scale_from_bounds(lo, hi, 0.01)
+        hs.append(kpm.Hamiltonian(op, a, b, prec))
+    Ms, Rs = [40, 64, 90, 50, 33, 128], [3, 4, 3, 5, 2, 4]
+    seeds, insts = [5, 6, 7, 8, 9, 10], [1, 2, 3, 4, 5, 6]
+    solo = [kpm.moments(h, Ms[k], Rs[k], wl.VEC_PHASE, seeds[k], insts[k]).cpu().numpy() for k, h in enumerate(hs)]
+    for wave in (1, 0, 192):
+        with kpm.launch_settings(wave_mib=wave):
+            got = [m.cpu().numpy() for m in kpm.moments_batched(hs, Ms, Rs, wl.VEC_PHASE, seeds, insts)]
+        for k in range(len(hs)):
+            assert np.array_equal(got[k], solo[k]), (wave, k)
+    for h in hs:
+        h.free()
+
+
 def test_mixed_operator_batch():
     ops = [wl.square_lattice(20, W=1.0, seed=40), wl.spin_cubic_lattice(6, seed=41), wl.cubic_lattice(7, W=1.0, seed=42)]
     hs = []

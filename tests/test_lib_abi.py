@@ -94,9 +94,9 @@ def test_argument_validation_without_device(L):
 def test_launch_settings_roundtrip(L):
     old = kpm.get_launch()
     with kpm.launch_settings(elems_per_thread=2, max_blocks=1024, march=0, march_items=64, xcd_split=3, alternate=0,
-                             small=0, streaming=0):
+                             small=0, streaming=0, wave_mib=0):
         assert kpm.get_launch() == {"elems_per_thread": 2, "max_blocks": 1024, "march": 0, "march_items": 64,
-                                    "xcd_split": 3, "alternate": 0, "small": 0, "streaming": 0}
+                                    "xcd_split": 3, "alternate": 0, "small": 0, "streaming": 0, "wave_mib": 0}
     assert kpm.get_launch() == old
 
 
@@ -106,3 +106,42 @@ def test_no_cpu_fallback_when_library_missing(monkeypatch):
     monkeypatch.setattr(kpm, "_LIB_PATH", "/nonexistent/libkpm.so")
     with pytest.raises(kpm.KPMError):
         kpm.lib()
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_block_placement(L, case):
+    """Multi-instance launches: every block of the grid maps to one block of one instance or is idle;
+    instances split per XCD start on a multiple of 8; every other instance has all its blocks on
+    one XCD (block b runs on XCD b mod 8)."""
+    g = np.random.default_rng(case)
+    n = [1, 3, 8, 9, 17, 256][case]
+    nb = (g.integers(1, 40, n) * 8).astype(np.uint32)
+    xcd = (g.random(n) < 0.3).astype(np.int32)
+    if case == 0:
+        xcd[:] = 0
+    b0 = np.zeros(n, np.uint32)
+    bs = np.zeros(n, np.uint32)
+    cap = int(nb.sum()) * 2 + 8 * int(nb.max())
+    m = np.zeros(cap, np.uint32)
+    P = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    blocks = L.kpm_selftest_placement(P(nb), P(xcd), n, P(b0), P(bs), P(m), cap)
+    assert blocks > 0
+    m = m[:blocks]
+    seen = [set() for _ in range(n)]
+    for blk, i in enumerate(m):
+        if i == 0xFFFFFFFF:
+            continue
+        assert i < n
+        off = blk - int(b0[i])
+        assert off >= 0 and off % bs[i] == 0
+        j = off // bs[i]
+        assert j < nb[i] and j not in seen[i]
+        seen[i].add(j)
+    for i in range(n):
+        assert len(seen[i]) == nb[i]
+        if xcd[i]:
+            assert bs[i] == 1 and b0[i] % 8 == 0
+        else:
+            assert bs[i] == 8
+    idle = int((m == 0xFFFFFFFF).sum())
+    assert idle <= 8 * int(nb.max()) + blocks // 4
