@@ -34,6 +34,8 @@ WORKLOAD_TEXT = {
                "vectors, FP32 recursion, FP64 moments, Jackson DoS on 8192 points",
     "config3": "batch of 256 3D cubic spin-hopping lattices, L uniform in 16..48, base texture with 1-8 spins "
                "re-drawn, M=512, R=16 random-phase vectors, complex64 recursion, FP64 moments, one captured graph",
+    "config5": "Poisson stream of KPM DoS requests: N log-uniform from 2^12 sites, 2D/3D, real (Anderson) or spin "
+               "hopping, M in {256,1024,4096,8192}, R in [8,64]; FP32 continuous batching vs plain FP64 FCFS",
 }
 
 
@@ -159,8 +161,10 @@ def pmc_summary(root):
 def serving_leg(n_requests, logN_max, load, seed=1005):
     """Config-5 recipe (Poisson arrivals; N log-uniform from 2^12 up to 2^logN_max; 2D/3D; real or
     spin hopping; M in {256, 1024, 4096, 8192}; R in [8, 64]).  Capacity of the batched FP32 server
-    is measured with every request present at t = 0; a wall-clock trace at `load` x capacity is then
-    served by it and replayed through the plain FP64 first-come-first-served path (one solve at a time)."""
+    is measured with every request present at t = 0; a wall-clock trace at each offered load
+    (`load`: one value or a list) x capacity is then served by it and replayed through the plain
+    FP64 first-come-first-served path (one solve at a time)."""
+    loads = [load] if isinstance(load, (int, float)) else list(load)
     import numpy as np
     import paper_1105_5481_amd as kpm
     from paper_1105_5481_amd import workloads as wl
@@ -185,23 +189,35 @@ def serving_leg(n_requests, logN_max, load, seed=1005):
     assert all(r.status == "ok" for r in res)
     capacity = n_requests / makespan
     gaps = np.diff([0.0] + [r.arrival for r in stream])
-    arrivals = np.cumsum(gaps / (load * capacity))
-    log(f"bench: serving capacity {capacity:.1f} req/s; trace of {n_requests} requests over {arrivals[-1]:.2f} s")
-    srv = Server(prec=kpm.F32, max_active=64, chunk=32)
-    served = srv.run(reqs(arrivals), clock="wall")
-    conc = srv.max_concurrent
-    srv.close()
-    srv = Server(prec=kpm.F64, max_active=1, chunk=64)
-    plain = srv.run(reqs(arrivals), clock="wall")
-    srv.close()
-    svc64 = np.array([r.t_done - r.t_admit for r in plain if r.status == "ok"])
-    return {"requests": n_requests, "logN_range": [12, logN_max], "offered_load": load,
-            "fp32_capacity_req_per_s": capacity, "fp32_throughput_updates_per_s": updates / makespan,
-            "fp32_throughput_GBps_algorithmic": alg_bytes / makespan / 1e9,
+    log(f"bench: serving capacity {capacity:.1f} req/s ({n_requests} requests, makespan {makespan:.1f} s)")
+    out = {"requests": n_requests, "logN_range": [12, logN_max],
+           "fp32_capacity_req_per_s": capacity, "fp32_throughput_updates_per_s": updates / makespan,
+           "fp32_throughput_GBps_algorithmic": alg_bytes / makespan / 1e9, "loads": []}
+    for ld in loads:
+        arrivals = np.cumsum(gaps / (ld * capacity))
+        log(f"bench: load {ld}: trace over {arrivals[-1]:.2f} s")
+        srv = Server(prec=kpm.F32, max_active=64, chunk=32)
+        served = srv.run(reqs(arrivals), clock="wall")
+        conc = srv.max_concurrent
+        srv.close()
+        log(f"bench: load {ld}: FP32 served {latency_stats(served)}")
+        srv = Server(prec=kpm.F64, max_active=1, chunk=64)
+        plain = srv.run(reqs(arrivals), clock="wall")
+        srv.close()
+        svc64 = np.array([r.t_done - r.t_admit for r in plain if r.status == "ok"])
+        cap64 = len(svc64) / svc64.sum()
+        log(f"bench: load {ld}: FP64 FCFS {latency_stats(plain)}")
+        out["loads"].append({
+            "offered_load": ld, "arrival_rate_req_per_s": ld * capacity,
             "fp32_served": latency_stats(served), "max_concurrent_solves": conc,
             "fp64_fcfs": latency_stats(plain),
             "fp64_isolated_service_ms": {"p50": float(np.percentile(svc64, 50) * 1e3),
-                                         "p99": float(np.percentile(svc64, 99) * 1e3)}}
+                                         "p99": float(np.percentile(svc64, 99) * 1e3),
+                                         "mean": float(svc64.mean() * 1e3)},
+            "fp64_capacity_req_per_s": cap64, "fp64_stable_at_this_rate": bool(ld * capacity < cap64)})
+    if len(loads) == 1:      # flat layout for the single-load leg of the default run
+        out.update(out.pop("loads")[0])
+    return out
 
 
 def cpu_baseline(lat, a, b, vec, seed):
@@ -229,7 +245,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=160)
     ap.add_argument("--serve-logn-max", type=float, default=18.0)
-    ap.add_argument("--serve-load", type=float, default=0.7)
+    ap.add_argument("--serve-load", type=lambda v: [float(x) for x in v.split(",")], default=[0.7],
+                    help="offered load(s) as a fraction of the measured FP32 capacity, comma separated")
     ap.add_argument("--tpt", type=int, default=0, help="chunks per thread per tile (1, 2, 4)")
     ap.add_argument("--max-blocks", type=int, default=0)
     ap.add_argument("--march", type=int, default=-1, help="1: march kernels for lattices, 0: flat kernels")
@@ -242,8 +259,8 @@ def main():
                     help="first run a plain 1 GiB device copy three times (counter calibration under rocprofv3)")
     ap.add_argument("--pmc-summary", metavar="DIR",
                     help="print per-kernel averages of rocprofv3 --pmc CSV files found under DIR and exit")
-    ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config4"],
-                    help="config2 (the measured workload) or config4 (2D 2048^2, R=64, real FP32) for exploration")
+    ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config4", "config5"],
+                    help="config2 (the measured workload), config3 (256-cube batch), config4 (2D 2048^2, R=64, real FP32), config5 (serving record)")
     args = ap.parse_args()
 
     if args.pmc_summary:
@@ -279,6 +296,13 @@ def main():
     dev = "cuda"
     stream = torch.cuda.current_stream()
 
+    if args.workload == "config5":
+        # the serving record alone: FP32 continuous batching vs the plain FP64 FCFS path
+        sv = serving_leg(args.serve_requests, args.serve_logn_max, args.serve_load)
+        print(json.dumps({"metric": "p50/p99 solve latency under a Poisson request stream", "unit": "ms",
+                          "n_gpus": 1, "data": "synthetic", "higher_is_better": False,
+                          "config": {"workload": WORKLOAD_TEXT["config5"]}, "serving": sv}), flush=True)
+        return
     if args.workload == "config3":
         print(json.dumps(bench_batched(args, log)), flush=True)
         return
@@ -382,7 +406,7 @@ def main():
 
     if not args.no_serve:
         log("bench: serving leg")
-        out["serving"] = serving_leg(args.serve_requests, args.serve_logn_max, args.serve_load)
+        out["serving"] = serving_leg(args.serve_requests, args.serve_logn_max, args.serve_load[0])
 
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on a bounded sample")

@@ -20,7 +20,7 @@ constexpr int PSLOTS_MAX = 64;          // ring slots of per-tile partials betwe
 int g_tpt = 4;                          // flat kernels: chunks per thread per tile
 int g_max_blocks = 2048;                // blocks per instance per launch (multiple of 8)
 int g_march = 1;                        // lattices use the march kernels
-int g_march_items = 1024;               // target work items per instance when choosing march segments
+int g_march_items = 512;                // target work items per instance when choosing march segments
 int g_xcd_split = 0;                    // 0 automatic, 1 by column tiles, 2 by segments, 3 none
 int g_alternate = 1;                    // march: odd segments walk downwards
 int g_small = 1;                        // solves whose two vector blocks fit in LDS run in one workgroup
@@ -975,15 +975,22 @@ kpm_status kpm_moments(kpm_ham *h, int32_t M, int32_t R, int32_t vec, uint64_t s
 namespace {
 // Block placement of one launch group (instances of one kernel class, in table
 // order).  Instances whose work is split per XCD take a contiguous,
-// 8-aligned block range.  The others are packed in octets of similar size:
-// instance k of an octet owns blocks region + k + 8 j (stride 8), so all its
-// blocks run on one XCD and its in-plane neighbours stay in that XCD's L2.
+// 8-aligned block range (every nb is a multiple of 8).  When there are at
+// least 8 of the others, they are packed in octets of similar size: instance k
+// of an octet owns blocks region + k + 8 j (stride 8), so all its blocks run
+// on one XCD and its in-plane neighbours stay in that XCD's L2.  Fewer than 8
+// are placed contiguously, so each still spreads over the whole chip.
 // Writes block0/bstride into the instances and the per-block map (instance
 // index within the group, NO_INSTANCE for idle blocks); returns the grid size.
 uint32_t place_blocks(std::vector<Inst> &ins, std::vector<uint32_t> &map)
 {
     std::vector<uint32_t> big, small;
     for (uint32_t r = 0; r < ins.size(); ++r) (ins[r].xcd ? big : small).push_back(r);
+    if (small.size() < 8) {
+        big.insert(big.end(), small.begin(), small.end());
+        std::sort(big.begin(), big.end());
+        small.clear();
+    }
     std::sort(small.begin(), small.end(), [&](uint32_t a, uint32_t b) { return ins[a].nb > ins[b].nb; });
     uint32_t blocks = 0;
     for (uint32_t r : big) {

@@ -137,11 +137,13 @@ def test_block_placement(L, case):
         j = off // bs[i]
         assert j < nb[i] and j not in seen[i]
         seen[i].add(j)
+    packed = int((xcd == 0).sum()) >= 8
     for i in range(n):
         assert len(seen[i]) == nb[i]
-        if xcd[i]:
+        if xcd[i] or not packed:
             assert bs[i] == 1 and b0[i] % 8 == 0
         else:
             assert bs[i] == 8
+            assert len({(int(b0[i]) + 8 * j) % 8 for j in range(int(nb[i]))}) == 1
     idle = int((m == 0xFFFFFFFF).sum())
     assert idle <= 8 * int(nb.max()) + blocks // 4
