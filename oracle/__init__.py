@@ -71,6 +71,10 @@ def _load():
         lib.kpmo_gershgorin_lattice.restype = i32
         lib.kpmo_gershgorin_csr.argtypes = [i64, P, P, P, P, P, P]
         lib.kpmo_gershgorin_csr.restype = i32
+        lib.kpmo_lanczos_lattice.argtypes = [i32, P, f64, i32, P, P, f64, f64, i32, i32, u64, u64, i32, P, P]
+        lib.kpmo_lanczos_lattice.restype = i32
+        lib.kpmo_lanczos_csr.argtypes = [i64, P, P, P, P, f64, f64, i32, i32, u64, u64, i32, P, P]
+        lib.kpmo_lanczos_csr.restype = i32
         lib.kpmo_max_threads.argtypes = []
         lib.kpmo_max_threads.restype = i32
         _lib = lib
@@ -139,6 +143,74 @@ def scale_from_bounds(e_lo: float, e_hi: float, eps: float = 0.01):
     """alpha_- and alpha_+ of Eq. (tilde) with a relative safety margin eps:
     a = (E_hi - E_lo) / (2 - eps), b = (E_hi + E_lo) / 2  (eps = 0 is the paper's literal choice)."""
     return (e_hi - e_lo) / (2.0 - eps), (e_hi + e_lo) / 2.0
+
+
+# --------------------------------------------------------------------------
+# Lanczos estimate of the spectral interval (an alternative to the Gershgorin
+# bounds of Sec. II-A for the rescaling of Eq. (tilde))
+# --------------------------------------------------------------------------
+def lanczos_lattice(dim, L, t, a, b, k, vec_kind=VEC_RADEMACHER, seed=0, instance=0, hop=HOP_REAL,
+                    onsite=None, spinor=None, nthreads=0):
+    """Lanczos coefficients (alpha_0..alpha_{k-1}, beta_0..beta_{k-1}) of H~ = (H - b)/a on a
+    periodic lattice, from start vector r = 0 of the given kind (the process in kpm_oracle.c)."""
+    Lv = np.ascontiguousarray(list(L) + [1] * (3 - len(L)), dtype=np.int64)
+    al = np.zeros(k)
+    be = np.zeros(k)
+    st = _load().kpmo_lanczos_lattice(dim, _ptr(Lv), float(t), hop, _ptr(_f64(onsite)), _ptr(_f64(spinor)),
+                                      float(a), float(b), k, vec_kind, seed, instance, nthreads, _ptr(al),
+                                      _ptr(be))
+    if st:
+        raise ValueError(f"oracle lanczos_lattice failed ({st})")
+    return al, be
+
+
+def lanczos_csr(row_ptr, col, val_re, val_im, a, b, k, vec_kind=VEC_RADEMACHER, seed=0, instance=0, nthreads=0):
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    cl = np.ascontiguousarray(col, dtype=np.int32)
+    al = np.zeros(k)
+    be = np.zeros(k)
+    st = _load().kpmo_lanczos_csr(len(rp) - 1, _ptr(rp), _ptr(cl), _ptr(_f64(val_re)), _ptr(_f64(val_im)),
+                                  float(a), float(b), k, vec_kind, seed, instance, nthreads, _ptr(al), _ptr(be))
+    if st:
+        raise ValueError(f"oracle lanczos_csr failed ({st})")
+    return al, be
+
+
+LANCZOS_BREAKDOWN = 1e-12
+
+
+def lanczos_bounds(alpha, beta, a=1.0, b=0.0, pad=0.005, clamp=(-np.inf, np.inf)):
+    """Spectral interval of H from the Lanczos coefficients of H~ = (H - b)/a.
+
+    The process stops at the first j with beta_j <= 1e-12 max(|alpha|, |beta| up to j) (an
+    invariant subspace), giving m = j + 1 coefficients; else m = k.  T is the m x m symmetric
+    tridiagonal matrix with diagonal alpha_0..alpha_{m-1} and off-diagonal beta_0..beta_{m-2}.
+    Its extreme eigenpairs (theta, y) come from a dense symmetric eigensolver; the residual bound
+    of a Ritz pair is r = beta_{m-1} |y_{m-1}| (0 after a breakdown).  The interval of H~ is
+    [theta_min - p_min, theta_max + p_max] with p = max(r, pad (theta_max - theta_min)), mapped to
+    H by E = a lambda + b and clipped to `clamp` (an interval known to enclose the spectrum,
+    e.g. the Gershgorin one).  Returns a dict with e_lo, e_hi, theta_min, theta_max, r_min, r_max, m."""
+    alpha = np.asarray(alpha, dtype=np.float64)
+    beta = np.asarray(beta, dtype=np.float64)
+    k = len(alpha)
+    m, scale, stop = k, 0.0, False
+    for j in range(k):
+        scale = max(scale, abs(alpha[j]), abs(beta[j]))
+        if beta[j] <= LANCZOS_BREAKDOWN * scale:
+            m, stop = j + 1, True
+            break
+    T = np.diag(alpha[:m]) + np.diag(beta[:m - 1], 1) + np.diag(beta[:m - 1], -1)
+    w, V = np.linalg.eigh(T)
+    blast = 0.0 if stop else beta[m - 1]
+    th_lo, th_hi = float(w[0]), float(w[-1])
+    r_lo, r_hi = blast * abs(V[m - 1, 0]), blast * abs(V[m - 1, -1])
+    width = th_hi - th_lo
+    lo = th_lo - max(r_lo, pad * width)
+    hi = th_hi + max(r_hi, pad * width)
+    e_lo = max(a * lo + b, clamp[0])
+    e_hi = min(a * hi + b, clamp[1])
+    return {"e_lo": e_lo, "e_hi": e_hi, "theta_min": th_lo, "theta_max": th_hi, "r_min": float(r_lo),
+            "r_max": float(r_hi), "m": m}
 
 
 # --------------------------------------------------------------------------
