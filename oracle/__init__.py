@@ -291,3 +291,50 @@ def dos(mu, K: int, a: float, b: float, use_jackson: bool = True):
     w[1:] *= 2.0
     f = (w[:, None] * cosnt).sum(axis=0) / (np.pi * np.sin(theta))
     return a * x + b, f / a
+
+
+# --------------------------------------------------------------------------
+# Green's functions from the same moments (the paper names Green's functions
+# beside the DoS as targets of the expansion, Sec. I; formulas below are the
+# standard Chebyshev-expansion ones of the KPM literature it cites)
+# --------------------------------------------------------------------------
+KERNEL_NONE, KERNEL_JACKSON, KERNEL_LORENTZ = 0, 1, 2
+
+
+def lorentz(M: int, lam: float) -> np.ndarray:
+    """Lorentz kernel g_n = sinh(lam (1 - n/M)) / sinh(lam), n = 0..M-1."""
+    n = np.arange(M, dtype=np.float64)
+    return np.sinh(lam * (1.0 - n / M)) / np.sinh(lam)
+
+
+def kernel_coeffs(M: int, kernel: int, lam: float = 4.0) -> np.ndarray:
+    if kernel == KERNEL_NONE:
+        return np.ones(M)
+    if kernel == KERNEL_JACKSON:
+        return jackson(M)
+    if kernel == KERNEL_LORENTZ:
+        return lorentz(M, lam)
+    raise ValueError(f"unknown kernel {kernel}")
+
+
+def green(mu, K: int, a: float, b: float, kernel: int = KERNEL_LORENTZ, lam: float = 4.0):
+    """Retarded Green's function G(omega) = <xi|(omega + i0 - H)^{-1}|xi> (per unit <xi|xi>) from the
+    moments of xi, on the K Chebyshev points: with x = cos(theta), s = sin(theta),
+        G~(x) = -(i/s) [g_0 mu_0 + 2 sum_{n>=1} g_n mu_n e^{-i n theta}],
+    i.e. Im G~ = -(1/s) sum_n w_n cos(n theta) (= -pi f(x) of Eq. (fKPM)) and
+    Re G~ = -(1/s) sum_{n>=1} w_n sin(n theta), w_n = (2 - delta_n0) g_n mu_n; then omega = a x + b and
+    G(omega) = G~(x)/a.  cos and sin of n theta_k use the exact reduction m = n (2k+1) mod 4K."""
+    mu = np.asarray(mu, dtype=np.float64)
+    M = len(mu)
+    g = kernel_coeffs(M, kernel, lam)
+    theta, x = chebyshev_points(K)
+    n = np.arange(M, dtype=np.int64)[:, None]
+    k = np.arange(K, dtype=np.int64)[None, :]
+    m = (n * (2 * k + 1)) % (4 * K)
+    ang = np.pi * m / (2.0 * K)
+    w = g * mu
+    w[1:] *= 2.0
+    fc = (w[:, None] * np.cos(ang)).sum(axis=0)
+    fs = (w[:, None] * np.sin(ang)).sum(axis=0)
+    s = np.sin(theta)
+    return a * x + b, (-fs / s - 1j * fc / s) / a
