@@ -110,6 +110,34 @@ const char *kpm_status_string(kpm_status st);
  * bounds_dev: device array of 2 doubles receiving (E_lo, E_hi). */
 kpm_status kpm_bounds_gershgorin(const kpm_ham_desc *desc, double *bounds_dev, void *stream);
 
+/* Lanczos estimate of the spectral interval (an alternative to Gershgorin for
+ * the rescaling of Eq. (tilde); the process itself is the textbook three-term
+ * recurrence, not part of the paper).  h must be an FP64 operator (any a, b;
+ * a = 1, b = 0 gives H itself).  From one start vector (random phases for a
+ * complex operator, +-1 otherwise; Philox key (seed, 4), vector 0, instance 0)
+ * it runs k steps
+ *   v_0 = xi/||xi||;  u = H~ v_j,  alpha_j = Re<v_j|u>,
+ *   w = (u - alpha_j v_j) - beta_{j-1} v_{j-1},  beta_j = ||w||,  v_{j+1} = w/beta_j
+ * with double-double dot products, then on the device takes the extreme
+ * eigenvalues theta of the tridiagonal matrix T_m (m = k, or fewer when some
+ * beta_j <= 1e-12 max(|alpha_i|, beta_i; i <= j), an invariant subspace), their
+ * residual bounds r = beta_{m-1} |y_{m-1}| (0 after such a breakdown), and
+ *   [theta_min - max(r_min, pad w), theta_max + max(r_max, pad w)],  w = theta_max - theta_min,
+ * mapped to H by E = a lambda + b and clipped to [clamp_lo, clamp_hi] (pass an
+ * interval known to enclose the spectrum, such as Gershgorin's, or +-inf).
+ * Ritz values lie inside the spectrum and approach its ends from inside, so
+ * the padding is what makes the interval enclose it; a too small interval shows
+ * up as moments above 1 in modulus.
+ * out_dev: device array of 8 + 2k doubles:
+ *   [0] E_lo, [1] E_hi, [2] theta_min, [3] theta_max, [4] r_min, [5] r_max
+ *   (these four in units of H~), [6] m, [7] 0, [8 + j] alpha_j, [8 + k + j] beta_j.
+ * 1 <= k <= 512, pad >= 0.  workspace_dev: kpm_lanczos_workspace_bytes(h, k)
+ * bytes, 256-byte aligned.  KPM_ERR_UNSUPPORTED for an FP32 operator. */
+size_t kpm_lanczos_workspace_bytes(const kpm_ham *h, int32_t k);
+kpm_status kpm_bounds_lanczos(kpm_ham *h, int32_t k, uint64_t seed, double pad, double clamp_lo,
+                              double clamp_hi, void *workspace_dev, size_t ws_bytes, double *out_dev,
+                              void *stream);
+
 /* Build the scaled operator H~ = (H - b)/a (Eq. (tilde)) in device memory that
  * the handle owns (one hipMalloc, released by kpm_free), in the recursion
  * precision `prec`.  The FP64 values are formed as d_i = (H_ii - b)/a and
@@ -228,6 +256,27 @@ void kpm_graph_free(kpm_graph *g);
  * when jackson != 0, else g_n = 1.  mu_dev[M], omega_dev[K], rho_dev[K]. */
 kpm_status kpm_dos(const double *mu_dev, int32_t M, int32_t jackson, int32_t K, double a,
                    double b, double *omega_dev, double *rho_dev, void *stream);
+
+/* Green's function from the moments of a start vector xi (per unit <xi|xi>):
+ *   G(omega) = <xi|(omega + i0 - H)^{-1}|xi>,
+ * expanded on the K first-kind Chebyshev points x_k = cos theta_k,
+ * theta_k = pi (k + 1/2)/K, as
+ *   G~(x) = -(i / sin theta) [g_0 mu_0 + 2 sum_{n>=1} g_n mu_n e^{-i n theta}],
+ *   omega_k = a x_k + b,  G(omega_k) = G~(x_k)/a,
+ * so Im G = -pi rho (Eq. (fKPM)) and Re G is its Hilbert transform.  The
+ * kernel damps the truncation: KPM_KERNEL_NONE (g_n = 1), KPM_KERNEL_JACKSON,
+ * KPM_KERNEL_LORENTZ (g_n = sinh(lambda (1 - n/M))/sinh(lambda), 0 < lambda <
+ * 700; it broadens each level to a Lorentzian of half-width ~ lambda/M in
+ * theta, the usual choice for Green's functions).  The paper names Green's
+ * functions beside the DoS as targets of the expansion (Sec. I); with unit
+ * start vectors at chosen sites (KPM_VEC_UNIT, R = 1, instance = site, one
+ * batched solve per site) the moments are those of the local DoS and G is the
+ * site-diagonal Green's function.  FP64; all arrays are device arrays
+ * (omega, g_re, g_im of K doubles). */
+typedef enum { KPM_KERNEL_NONE = 0, KPM_KERNEL_JACKSON = 1, KPM_KERNEL_LORENTZ = 2 } kpm_kernel;
+kpm_status kpm_green(const double *mu_dev, int32_t M, int32_t kernel, double lambda, int32_t K,
+                     double a, double b, double *omega_dev, double *g_re_dev, double *g_im_dev,
+                     void *stream);
 
 /* The start vectors r_0 exactly as the recursion draws them, in FP64, layout
  * [i][r] (real) or [i][r][2] (complex, re/im) with i < N, r < R.  complex_layout

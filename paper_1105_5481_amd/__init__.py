@@ -21,6 +21,7 @@ F64, F32 = 0, 1
 VEC_RADEMACHER, VEC_PHASE, VEC_UNIT = 0, 1, 2
 KIND_SQUARE_2D, KIND_CUBIC_3D, KIND_CSR = 2, 3, 10
 HOP_REAL, HOP_SPIN = 0, 1
+KERNEL_NONE, KERNEL_JACKSON, KERNEL_LORENTZ = 0, 1, 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libkpm.so")
@@ -87,6 +88,9 @@ def lib():
         "kpm_graph_capture_batched": (i32, [P, i32, P, P, i32, P, P, P, sz, P, P, P]),
         "kpm_graph_launch": (i32, [P, P]),
         "kpm_graph_free": (None, [P]),
+        "kpm_lanczos_workspace_bytes": (sz, [P, i32]),
+        "kpm_green": (i32, [P, i32, i32, f64, i32, f64, f64, P, P, P, P]),
+        "kpm_bounds_lanczos": (i32, [P, i32, u64, f64, f64, f64, P, sz, P, P]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(L, name)
@@ -170,6 +174,42 @@ def gershgorin(op, device="cuda", stream=None):
     torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
     lo, hi = out.tolist()
     return lo, hi
+
+
+def lanczos_bounds(ham: "Hamiltonian", k: int = 100, seed: int = 0, pad: float = 0.005, clamp="gershgorin",
+                   stream=None) -> dict:
+    """Spectral interval of H from k Lanczos steps on the FP64 operator `ham` (kpm_bounds_lanczos):
+    the extreme Ritz values padded by max(residual bound, pad x their spread), mapped back through
+    the operator's (a, b) and clipped to `clamp` ("gershgorin": the device Gershgorin interval of
+    ham.op; None: no clipping; or an (E_lo, E_hi) pair).  Returns e_lo, e_hi, theta_min, theta_max,
+    r_min, r_max (these four for H~), m (steps used) and the alpha, beta arrays."""
+    torch = _torch()
+    if isinstance(clamp, str) and clamp == "gershgorin":
+        clamp = gershgorin(ham.op, ham.device, stream)
+    lo, hi = (-float("inf"), float("inf")) if clamp is None else (float(clamp[0]), float(clamp[1]))
+    nb = lib().kpm_lanczos_workspace_bytes(ham.handle, int(k))
+    if nb == 0:
+        raise KPMError(f"Lanczos bounds need an FP64 operator and 1 <= k <= 512 (k={k})")
+    ws = _workspace(nb, ham.device)
+    out = torch.empty(8 + 2 * int(k), dtype=torch.float64, device=ham.device)
+    _check(lib().kpm_bounds_lanczos(ham.handle, int(k), int(seed), float(pad), lo, hi, ws.data_ptr(), nb,
+                                    out.data_ptr(), _stream(stream)), "kpm_bounds_lanczos")
+    o = out.cpu().numpy()
+    return {"e_lo": float(o[0]), "e_hi": float(o[1]), "theta_min": float(o[2]), "theta_max": float(o[3]),
+            "r_min": float(o[4]), "r_max": float(o[5]), "m": int(o[6]), "alpha": o[8:8 + k].copy(),
+            "beta": o[8 + k:8 + 2 * k].copy()}
+
+
+def lanczos_scale(op, k: int = 100, eps: float = 0.01, pad: float = 0.005, seed: int = 0, device="cuda",
+                  stream=None):
+    """(a, b) of Eq. (tilde) from the Lanczos interval of `op` (clipped to Gershgorin), with the
+    relative margin eps of scale_from_bounds."""
+    h = Hamiltonian(op, 1.0, 0.0, F64, device, stream)
+    try:
+        r = lanczos_bounds(h, k, seed, pad, "gershgorin", stream)
+    finally:
+        h.free()
+    return scale_from_bounds(r["e_lo"], r["e_hi"], eps)
 
 
 class Hamiltonian:
@@ -426,6 +466,58 @@ def dos(mu, K: int, a: float, b: float, jackson: bool = True, stream=None):
     _check(lib().kpm_dos(mu.data_ptr(), M, 1 if jackson else 0, K, float(a), float(b), om.data_ptr(),
                          rho.data_ptr(), _stream(stream)), "kpm_dos")
     return om, rho
+
+
+def green(mu, K: int, a: float, b: float, kernel: int = KERNEL_LORENTZ, lam: float = 4.0, stream=None):
+    """(omega, G) device tensors (G complex128) of the Green's function <xi|(omega + i0 - H)^{-1}|xi>
+    from the moments of xi (kpm_green) on K Chebyshev points."""
+    torch = _torch()
+    M = mu.numel()
+    om = torch.empty(K, dtype=torch.float64, device=mu.device)
+    gre = torch.empty(K, dtype=torch.float64, device=mu.device)
+    gim = torch.empty(K, dtype=torch.float64, device=mu.device)
+    _check(lib().kpm_green(mu.data_ptr(), M, int(kernel), float(lam), K, float(a), float(b), om.data_ptr(),
+                           gre.data_ptr(), gim.data_ptr(), _stream(stream)), "kpm_green")
+    return om, torch.complex(gre, gim)
+
+
+def site_moments(ham: "Hamiltonian", sites, M: int, stream=None) -> List:
+    """Moments <i|T_n(H~)|i> of the local DoS at each site i (unit start vector e_i): one batched
+    solve with R = 1 per site (KPM_VEC_UNIT with instance = i)."""
+    sites = [int(i) for i in sites]
+    if not sites:
+        return []
+    N = ham.N
+    if min(sites) < 0 or max(sites) >= N:
+        raise KPMError(f"site index out of range [0, {N})")
+    return moments_batched([ham] * len(sites), M, 1, VEC_UNIT, [0] * len(sites), sites, stream=stream)
+
+
+def ldos(ham: "Hamiltonian", sites, M: int, K: Optional[int] = None, jackson: bool = True, stream=None):
+    """Local DoS rho_i(omega) at each site: (omega [K], rho [len(sites), K]) device tensors."""
+    torch = _torch()
+    K = K or 2 * M
+    mus = site_moments(ham, sites, M, stream)
+    rows = []
+    om = None
+    for mu in mus:
+        om, rho = dos(mu, K, ham.a, ham.b, jackson, stream)
+        rows.append(rho)
+    return om, torch.stack(rows) if rows else None
+
+
+def site_green(ham: "Hamiltonian", sites, M: int, K: Optional[int] = None, kernel: int = KERNEL_LORENTZ,
+               lam: float = 4.0, stream=None):
+    """Site-diagonal Green's functions G_ii(omega + i0): (omega [K], G [len(sites), K] complex)."""
+    torch = _torch()
+    K = K or 2 * M
+    mus = site_moments(ham, sites, M, stream)
+    rows = []
+    om = None
+    for mu in mus:
+        om, G = green(mu, K, ham.a, ham.b, kernel, lam, stream)
+        rows.append(G)
+    return om, torch.stack(rows) if rows else None
 
 
 def start_vectors(vec: int, complex_layout: bool, seed: int, instance: int, N: int, R: int, device="cuda",

@@ -522,14 +522,14 @@ __global__ __launch_bounds__(BLOCK) void k_step_march(const Inst *__restrict__ t
         if (e < PC) {
             const uint32_t p = fdiv(e, I.fC), c = e - p * C;
             uint32_t x = p, y = 0;
-            if (D3) {
+            if constexpr (D3) {
                 y = fdiv(p, I.fLx);
                 x = p - y * Lx;
             }
             const uint32_t pxm = (x == 0) ? p + (Lx - 1) : p - 1;
             const uint32_t pxp = (x == Lx - 1) ? p - (Lx - 1) : p + 1;
             uint32_t pym = 0, pyp = 0;
-            if (D3) {
+            if constexpr (D3) {
                 pym = (y == 0) ? p + (Ly - 1) * Lx : p - Lx;
                 pyp = (y == Ly - 1) ? p - (Ly - 1) * Lx : p + Lx;
             }
@@ -555,7 +555,7 @@ __global__ __launch_bounds__(BLOCK) void k_step_march(const Inst *__restrict__ t
                 T nb[NS];
                 nb[0] = G::ld(cur, (pxm + P * m) * C + c);
                 nb[1] = G::ld(cur, (pxp + P * m) * C + c);
-                if (D3) {
+                if constexpr (D3) {
                     nb[2] = G::ld(cur, (pym + P * m) * C + c);
                     nb[3] = G::ld(cur, (pyp + P * m) * C + c);
                 }
@@ -574,7 +574,7 @@ __global__ __launch_bounds__(BLOCK) void k_step_march(const Inst *__restrict__ t
                     const S2 bxp = G::ldc(I.bond, i * DIM + 0);
                     hr[0] = bxm[0]; hi[0] = -bxm[1];
                     hr[1] = bxp[0]; hi[1] = bxp[1];
-                    if (D3) {
+                    if constexpr (D3) {
                         const S2 bym = G::ldc(I.bond, (pym + P * m) * DIM + 1);
                         const S2 byp = G::ldc(I.bond, i * DIM + 1);
                         hr[2] = bym[0]; hi[2] = -bym[1];
@@ -627,7 +627,7 @@ __device__ __forceinline__ void flat_elem(const Inst &I, uint32_t e, const void 
         const uint32_t yq = fdiv(i, I.fLx);
         const uint32_t x = i - yq * Lx;
         uint32_t y = yq, z = 0;
-        if (D3) {
+        if constexpr (D3) {
             z = fdiv(yq, I.fLy);
             y = yq - z * Ly;
         }
@@ -636,7 +636,7 @@ __device__ __forceinline__ void flat_elem(const Inst &I, uint32_t e, const void 
         nbi[1] = (x == Lx - 1) ? i - (Lx - 1) : i + 1;
         nbi[2] = (y == 0) ? i + (Ly - 1) * Lx : i - Lx;
         nbi[3] = (y == Ly - 1) ? i - (Ly - 1) * Lx : i + Lx;
-        if (D3) {
+        if constexpr (D3) {
             const uint32_t Pz = Lx * Ly, Lz = I.Lz;
             nbi[4] = (z == 0) ? i + (Lz - 1) * Pz : i - Pz;
             nbi[5] = (z == Lz - 1) ? i - (Lz - 1) * Pz : i + Pz;
@@ -752,7 +752,7 @@ __device__ __forceinline__ typename V16<S>::T small_elem(const Inst &I, uint32_t
         const uint32_t yq = fdiv(i, I.fLx);
         const uint32_t x = i - yq * Lx;
         uint32_t y = yq, z = 0;
-        if (D3) {
+        if constexpr (D3) {
             z = fdiv(yq, I.fLy);
             y = yq - z * Ly;
         }
@@ -761,7 +761,7 @@ __device__ __forceinline__ typename V16<S>::T small_elem(const Inst &I, uint32_t
         nbi[1] = (x == Lx - 1) ? i - (Lx - 1) : i + 1;
         nbi[2] = (y == 0) ? i + (Ly - 1) * Lx : i - Lx;
         nbi[3] = (y == Ly - 1) ? i - (Ly - 1) * Lx : i + Lx;
-        if (D3) {
+        if constexpr (D3) {
             const uint32_t Pz = Lx * Ly, Lz = I.Lz;
             nbi[4] = (z == 0) ? i + (Lz - 1) * Pz : i - Pz;
             nbi[5] = (z == Lz - 1) ? i - (Lz - 1) * Pz : i + Pz;

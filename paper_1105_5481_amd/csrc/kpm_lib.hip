@@ -11,6 +11,7 @@
 
 #include "kpm.h"
 #include "kpm_kernels.hpp"
+#include "kpm_lanczos.hpp"
 
 using namespace kpm;
 
@@ -289,42 +290,84 @@ __global__ __launch_bounds__(256) void k_bounds_csr(int64_t n, const int64_t *ro
 // density of states, Eq. (fKPM), one thread per Chebyshev point
 // ---------------------------------------------------------------------------
 constexpr int DOS_CHUNK = 2048;
-__global__ __launch_bounds__(256) void k_dos(const double *mu, int M, int jackson, int K, double a, double b,
-                                             double *omega, double *rho)
+// Kernel coefficient g_n of an M-moment expansion: 0 none, 1 Jackson
+// [(M-n+1) cos(pi n/(M+1)) + sin(pi n/(M+1)) cot(pi/(M+1))]/(M+1),
+// 2 Lorentz sinh(lam (1 - n/M))/sinh(lam).
+__device__ inline double kernel_coef(int kind, int n, int M, double lam, double cot1)
+{
+    if (kind == 1) {
+        const double x = (double)n / (double)(M + 1);
+        return ((double)(M - n + 1) * cospi(x) + sinpi(x) * cot1) / (double)(M + 1);
+    }
+    if (kind == 2) return sinh(lam * (1.0 - (double)n / (double)M)) / sinh(lam);
+    return 1.0;
+}
+
+// Sums over n of w_n cos(n theta_k) (and w_n sin(n theta_k) when fs is
+// wanted), w_n = (2 - delta_n0) g_n mu_n, for the thread's Chebyshev point
+// theta_k = pi (k + 1/2)/K; n theta_k is reduced exactly as pi m/(2K) with
+// m = n (2k+1) mod 4K.  Every thread of the block takes part (LDS staging).
+__device__ inline void chebyshev_sums(const double *mu, int M, int kind, double lam, int K, int k, double &fc,
+                                      double *fs)
 {
     __shared__ double w[DOS_CHUNK];
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t step = 2 * (uint64_t)k + 1, fourK = 4 * (uint64_t)K;
     const double inv2K = 1.0 / (2.0 * (double)K);
-    double f = 0.0;
+    const double cot1 = cospi(1.0 / (double)(M + 1)) / sinpi(1.0 / (double)(M + 1));
     uint64_t m = 0;                                   // n (2k+1) mod 4K for the current n
-    const double cq = cospi(1.0 / (double)(M + 1)), sq = sinpi(1.0 / (double)(M + 1));
+    fc = 0.0;
+    double s = 0.0;
     for (int n0 = 0; n0 < M; n0 += DOS_CHUNK) {
         const int nn = min(DOS_CHUNK, M - n0);
         __syncthreads();
         for (int u = threadIdx.x; u < nn; u += blockDim.x) {
             const int n = n0 + u;
-            double g = 1.0;
-            if (jackson) {
-                const double x = (double)n / (double)(M + 1);
-                g = ((double)(M - n + 1) * cospi(x) + sinpi(x) * (cq / sq)) / (double)(M + 1);
-            }
-            w[u] = (n == 0 ? 1.0 : 2.0) * g * mu[n];
+            w[u] = (n == 0 ? 1.0 : 2.0) * kernel_coef(kind, n, M, lam, cot1) * mu[n];
         }
         __syncthreads();
         if (k < K) {
             for (int u = 0; u < nn; ++u) {
-                f += w[u] * cospi((double)m * inv2K);
+                const double t = (double)m * inv2K;
+                fc += w[u] * cospi(t);
+                if (fs) s += w[u] * sinpi(t);
                 m += step;
                 if (m >= fourK) m -= fourK;
                 if (m >= fourK) m %= fourK;
             }
         }
     }
+    if (fs) *fs = s;
+}
+
+// density of states, Eq. (fKPM), one thread per Chebyshev point
+__global__ __launch_bounds__(256) void k_dos(const double *mu, int M, int jackson, int K, double a, double b,
+                                             double *omega, double *rho)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    double f;
+    chebyshev_sums(mu, M, jackson ? 1 : 0, 0.0, K, k, f, nullptr);
     if (k < K) {
         const double th = ((double)k + 0.5) / (double)K;
         omega[k] = a * cospi(th) + b;
         rho[k] = f / (M_PI * sinpi(th)) / a;
+    }
+}
+
+// Green's function G(omega + i0) = <xi|(omega + i0 - H)^{-1}|xi> from the
+// moments: with x = cos theta, G~(x) = -(i/sin theta) sum_n w_n e^{-i n theta},
+// G(omega) = G~(x)/a at omega = a x + b.
+__global__ __launch_bounds__(256) void k_green(const double *mu, int M, int kind, double lam, int K, double a,
+                                               double b, double *omega, double *gre, double *gim)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    double fc, fs;
+    chebyshev_sums(mu, M, kind, lam, K, k, fc, &fs);
+    if (k < K) {
+        const double th = ((double)k + 0.5) / (double)K;
+        const double sn = sinpi(th);
+        omega[k] = a * cospi(th) + b;
+        gre[k] = -fs / sn / a;
+        gim[k] = -fc / sn / a;
     }
 }
 
@@ -1417,12 +1460,126 @@ void kpm_graph_free(kpm_graph *g)
     delete g;
 }
 
+// ---------------------------------------------------------------------------
+// Lanczos spectral interval
+// ---------------------------------------------------------------------------
+extern "C++" {
+namespace {
+typedef void (*lz_matvec_fn)(const Inst *, const void *, void *, int32_t);
+template <bool WIDE>
+lz_matvec_fn lz_matvec_for(int opk)
+{
+    switch (opk) {
+    case OP_REAL2: return k_lz_matvec<OP_REAL2, WIDE>;
+    case OP_REAL3: return k_lz_matvec<OP_REAL3, WIDE>;
+    case OP_SPIN2: return k_lz_matvec<OP_SPIN2, WIDE>;
+    case OP_SPIN3: return k_lz_matvec<OP_SPIN3, WIDE>;
+    case OP_CSR_R: return k_lz_matvec<OP_CSR_R, WIDE>;
+    default: return k_lz_matvec<OP_CSR_C, WIDE>;
+    }
+}
+
+// One FP64 vector (R = 1) in the flat layout; dots indices 0 .. 2k + 2.
+bool lanczos_plan(const kpm_ham *h, int32_t k, Plan &p, int32_t &vec)
+{
+    if (!h || h->prec != KPM_F64 || k < 1 || k > LZ_KMAX) return false;
+    vec = h->cplx_op ? KPM_VEC_PHASE : KPM_VEC_RADEMACHER;
+    if (!make_plan(h, 2, 1, vec, p)) return false;
+    p.mode = MODE_FLAT;
+    const uint64_t per_tile = (uint64_t)BLOCK * p.tpt;
+    p.tiles = (uint32_t)((p.nel + per_tile - 1) / per_tile);
+    p.xcd = p.tiles >= XCD_MIN_ITEMS ? 1 : 0;
+    p.nb = std::min<uint32_t>((p.tiles + 7) / 8 * 8, (uint32_t)g_max_blocks);
+    p.K = 2 * k + 2;
+    p.P_slots = 2;
+    p.part_bytes = align256((size_t)p.P_slots * p.tiles * 4 * sizeof(double));
+    p.dots_bytes = align256((size_t)(p.K + 1) * 4 * sizeof(double));
+    p.buf_bytes = align256((size_t)h->N * p.Rs * p.esz);
+    return true;
+}
+}  // namespace
+}  // extern "C++"
+
+size_t kpm_lanczos_workspace_bytes(const kpm_ham *h, int32_t k)
+{
+    Plan p;
+    int32_t vec;
+    if (!lanczos_plan(h, k, p, vec)) return 0;
+    return align256(sizeof(Inst)) + p.part_bytes + p.dots_bytes + 3 * p.buf_bytes;
+}
+
+kpm_status kpm_bounds_lanczos(kpm_ham *h, int32_t k, uint64_t seed, double pad, double clamp_lo, double clamp_hi,
+                              void *ws, size_t ws_bytes, double *out_dev, void *stream)
+{
+    if (!h || !out_dev || k < 1 || k > LZ_KMAX || !(pad >= 0.0) || !std::isfinite(pad) || std::isnan(clamp_lo) ||
+        std::isnan(clamp_hi) || !(clamp_lo < clamp_hi))
+        return KPM_ERR_INVALID_ARG;
+    if (h->prec != KPM_F64) return KPM_ERR_UNSUPPORTED;
+    Plan p;
+    int32_t vec;
+    if (!lanczos_plan(h, k, p, vec)) return KPM_ERR_INVALID_ARG;
+    if (!ws || ((uintptr_t)ws & 255) || ws_bytes < kpm_lanczos_workspace_bytes(h, k)) return KPM_ERR_WORKSPACE;
+    if (ensure_phase_table() != KPM_OK) return KPM_ERR_DEVICE;
+    hipStream_t st = S(stream);
+    char *base = (char *)ws;
+    Inst I;
+    fill_inst(h, p, 2, 1, vec, seed, 0, base + align256(sizeof(Inst)), I);
+    void *vb[2] = {I.buf0, I.buf1};
+    void *ub = (char *)I.buf1 + p.buf_bytes;
+    Inst *tab = (Inst *)base;
+    const bool wide = p.wide != 0;
+    const lz_matvec_fn mv = wide ? lz_matvec_for<true>(h->opk) : lz_matvec_for<false>(h->opk);
+    auto update = wide ? k_lz_update<true> : k_lz_update<false>;
+    auto scale = wide ? k_lz_scale<true> : k_lz_scale<false>;
+    const dim3 grid(p.nb), blk(BLOCK);
+    kpm_status e = upload(tab, &I, sizeof(Inst), st);
+    if (e == KPM_OK) e = launch_init(KPM_F64, p.wide, tab, nullptr, p.nb, st);       // xi, <xi|xi> partials
+    if (e == KPM_OK) e = launch_reduce(tab, 1, -1, 1, st);                          // dots[0]
+    if (e == KPM_OK) {
+        hipLaunchKernelGGL(scale, grid, blk, 0, st, tab, vb[0], 0);                  // v_0
+        e = check_launch();
+    }
+    int cur = 0;
+    for (int32_t j = 0; j < k && e == KPM_OK; ++j) {
+        hipLaunchKernelGGL(mv, grid, blk, 0, st, tab, (const void *)vb[cur], ub, 2 * j + 1);
+        e = check_launch();
+        if (e == KPM_OK) e = launch_reduce(tab, 1, 2 * j, 1, st);
+        if (e == KPM_OK) {
+            hipLaunchKernelGGL(update, grid, blk, 0, st, tab, (const void *)ub, (const void *)vb[cur], vb[cur ^ 1], j);
+            e = check_launch();
+        }
+        if (e == KPM_OK) e = launch_reduce(tab, 1, 2 * j + 1, 1, st);
+        if (e == KPM_OK) {
+            hipLaunchKernelGGL(scale, grid, blk, 0, st, tab, vb[cur ^ 1], 2 * j + 2);
+            e = check_launch();
+        }
+        cur ^= 1;
+    }
+    if (e == KPM_OK) {
+        hipLaunchKernelGGL(k_lz_tridiag, dim3(1), dim3(64), 0, st, tab, k, pad, h->a, h->b, clamp_lo, clamp_hi,
+                           out_dev);
+        e = check_launch();
+    }
+    return e;
+}
+
 kpm_status kpm_dos(const double *mu_dev, int32_t M, int32_t jackson, int32_t K, double a, double b, double *omega_dev,
                    double *rho_dev, void *stream)
 {
     if (!mu_dev || !omega_dev || !rho_dev || M < 1 || K < 1 || !(a > 0.0) || !std::isfinite(b)) return KPM_ERR_INVALID_ARG;
     hipLaunchKernelGGL(k_dos, dim3((K + 255) / 256), dim3(256), 0, S(stream), mu_dev, M, jackson ? 1 : 0, K, a, b,
                        omega_dev, rho_dev);
+    return check_launch();
+}
+
+kpm_status kpm_green(const double *mu_dev, int32_t M, int32_t kernel, double lambda, int32_t K, double a, double b,
+                     double *omega_dev, double *g_re_dev, double *g_im_dev, void *stream)
+{
+    if (!mu_dev || !omega_dev || !g_re_dev || !g_im_dev || M < 1 || K < 1 || kernel < 0 || kernel > 2 ||
+        !(a > 0.0) || !std::isfinite(b) || (kernel == 2 && !(lambda > 0.0 && lambda < 700.0)))
+        return KPM_ERR_INVALID_ARG;
+    hipLaunchKernelGGL(k_green, dim3((K + 255) / 256), dim3(256), 0, S(stream), mu_dev, M, kernel, lambda, K, a, b,
+                       omega_dev, g_re_dev, g_im_dev);
     return check_launch();
 }
 

@@ -3,7 +3,8 @@
 Requests (a lattice or CSR Hamiltonian, M moments, R start vectors) arrive over time.  The
 loop below admits them first-come first-served while their device footprint (operator plus
 workspace, from the C ABI's kpm_request_bytes) fits the HBM budget and a batch slot is free.
-An admitted request gets its spectral bounds (device Gershgorin), its operator (kpm_build) and
+An admitted request gets its spectral bounds (device Gershgorin, or the tighter device Lanczos
+interval on request), its operator (kpm_build) and
 a begun solve whose vector state stays resident in its workspace.  Every loop iteration
 enqueues one chunk of recursion steps through kpm_batch_advance: each launch of the chunk covers
 all in-flight solves of an operator class, each at its own step, so requests that arrive while
@@ -24,8 +25,8 @@ from typing import Dict, List, Optional, Tuple
 
 import numpy as np
 
-from . import F32, F64, VEC_RADEMACHER, Batch, Hamiltonian, KPMError, Solve, dos, gershgorin, request_bytes, \
-    scale_from_bounds
+from . import F32, F64, VEC_RADEMACHER, Batch, Hamiltonian, KPMError, Solve, dos, gershgorin, lanczos_scale, \
+    request_bytes, scale_from_bounds
 
 
 @dataclass(eq=False)
@@ -37,8 +38,10 @@ class KPMRequest:
     seed: int = 0
     instance: int = 0
     K_dos: int = 0                  # DoS points (0: 2M)
-    eps: float = 0.01               # spectral margin for the Gershgorin scale
-    scale: Optional[Tuple[float, float]] = None   # explicit (a, b); else Gershgorin
+    eps: float = 0.01               # spectral margin of the scale
+    scale: Optional[Tuple[float, float]] = None   # explicit (a, b); else from `bounds`
+    bounds: str = "gershgorin"      # "gershgorin" or "lanczos" (interval from lanczos_k steps)
+    lanczos_k: int = 100
     arrival: float = 0.0            # seconds (wall clock) or chunk index (chunk clock)
     rid: int = -1
 
@@ -160,6 +163,8 @@ class Server:
             t_admit = self.now()
             if req.scale is not None:
                 a, b = req.scale
+            elif req.bounds == "lanczos":
+                a, b = lanczos_scale(req.op, req.lanczos_k, req.eps, device=self.device)
             else:
                 lo, hi = gershgorin(req.op, self.device)
                 a, b = scale_from_bounds(lo, hi, req.eps)

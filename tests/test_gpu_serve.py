@@ -129,3 +129,18 @@ def test_wall_clock_trace_latency():
     st = latency_stats(res)
     print("  latency", st)
     assert st["n"] == len(reqs) and st["p99_ms"] >= st["p50_ms"] > 0
+
+
+def test_lanczos_scaled_requests():
+    """Requests that ask for the Lanczos interval get a tighter scale than Gershgorin and the same
+    moments as a solo solve on that scale."""
+    reqs = [KPMRequest(op=wl.spin_cubic_lattice(18, seed=90 + k), M=128, R=4, vec=wl.VEC_PHASE, seed=k, arrival=0,
+                       rid=k, bounds="lanczos", lanczos_k=80) for k in range(3)]
+    srv = Server(prec=kpm.F32, max_active=4, chunk=32)
+    res = srv.run(reqs, clock="chunks")
+    srv.close()
+    for req, r in zip(reqs, res):
+        assert r.status == "ok"
+        lo, hi = oracle.gershgorin_lattice(3, (18, 18, 18), 1.0, 1, None, req.op.spinor)
+        assert r.a < oracle.scale_from_bounds(lo, hi, 0.01)[0]
+        assert np.array_equal(r.mu, _solo(req, kpm.F32, r.a, r.b))

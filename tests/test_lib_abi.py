@@ -91,6 +91,12 @@ def test_argument_validation_without_device(L):
     assert L.kpm_bounds_gershgorin(ctypes.byref(d), None, None) == 1
 
 
+def test_lanczos_argument_validation(L):
+    assert L.kpm_lanczos_workspace_bytes(None, 10) == 0
+    inf = float("inf")
+    assert L.kpm_bounds_lanczos(None, 10, 0, 0.005, -inf, inf, None, 0, None, None) == 1
+
+
 def test_launch_settings_roundtrip(L):
     old = kpm.get_launch()
     with kpm.launch_settings(elems_per_thread=2, max_blocks=1024, march=0, march_items=64, xcd_split=3, alternate=0,
