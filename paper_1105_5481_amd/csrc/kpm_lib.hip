@@ -1017,14 +1017,21 @@ kpm_status kpm_moments(kpm_ham *h, int32_t M, int32_t R, int32_t vec, uint64_t s
 // ---------------------------------------------------------------------------
 namespace {
 // Block placement of one launch group (instances of one kernel class, in table
-// order).  Instances whose work is split per XCD take a contiguous,
-// 8-aligned block range (every nb is a multiple of 8).  When there are at
-// least 8 of the others, they are packed in octets of similar size: instance k
-// of an octet owns blocks region + k + 8 j (stride 8), so all its blocks run
-// on one XCD and its in-plane neighbours stay in that XCD's L2.  Fewer than 8
-// are placed contiguously, so each still spreads over the whole chip.
-// Writes block0/bstride into the instances and the per-block map (instance
-// index within the group, NO_INSTANCE for idle blocks); returns the grid size.
+// order).  Instances whose work is split per XCD take contiguous, 8-aligned
+// block ranges (every nb is a multiple of 8).  When there are at least 8 of
+// the others they are balanced over the XCDs: largest first (by chunks, i.e.
+// work), each goes whole to the least loaded XCD if that stays within 10% of
+// an even share, and is otherwise split per XCD like the big ones (when it has
+// at least SPLIT_MIN_UNITS units to split).  The instances of XCD x take its blocks x, x + 8,
+// x + 16, ... one after another (block stride 8), so all blocks of such an
+// instance run on one XCD and the halo planes its neighbouring column tiles
+// fetch stay in that XCD's L2.  Fewer than 8 are placed contiguously, so each
+// still spreads over the whole chip.  Splitting changes only which block runs
+// a work item, never the items, so results do not depend on the placement.
+// Writes block0/bstride (and xcd for split instances) into the instances and
+// the per-block map (instance index within the group, NO_INSTANCE for idle
+// blocks); returns the grid size.
+constexpr uint32_t SPLIT_MIN_UNITS = 48;   // below this a split leaves too few units per XCD (halo re-fetch)
 uint32_t place_blocks(std::vector<Inst> &ins, std::vector<uint32_t> &map)
 {
     std::vector<uint32_t> big, small;
@@ -1034,7 +1041,30 @@ uint32_t place_blocks(std::vector<Inst> &ins, std::vector<uint32_t> &map)
         std::sort(big.begin(), big.end());
         small.clear();
     }
-    std::sort(small.begin(), small.end(), [&](uint32_t a, uint32_t b) { return ins[a].nb > ins[b].nb; });
+    auto cost = [&](uint32_t r) { return ins[r].nel ? (uint64_t)ins[r].nel : (uint64_t)ins[r].nb; };
+    auto units = [&](uint32_t r) { return ins[r].mode == MODE_MARCH ? ins[r].nct : ins[r].tiles; };
+    std::stable_sort(small.begin(), small.end(), [&](uint32_t a, uint32_t b) { return cost(a) > cost(b); });
+    uint64_t total = 0;
+    for (uint32_t r : small) total += cost(r);
+    const double share = (double)total / 8.0 * 1.10;
+    uint64_t load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    uint32_t used[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    std::vector<uint32_t> whole, xcd_of;
+    for (uint32_t r : small) {
+        int x = 0;
+        for (int y = 1; y < 8; ++y)
+            if (load[y] < load[x]) x = y;
+        if ((double)(load[x] + cost(r)) > share && units(r) >= SPLIT_MIN_UNITS && ins[r].nb >= 8) {
+            ins[r].xcd = 1;   // split over all XCDs by units
+            big.push_back(r);
+            for (int y = 0; y < 8; ++y) load[y] += cost(r) / 8;
+            continue;
+        }
+        whole.push_back(r);
+        xcd_of.push_back((uint32_t)x);
+        load[x] += cost(r);
+        used[x] += ins[r].nb;
+    }
     uint32_t blocks = 0;
     for (uint32_t r : big) {
         ins[r].block0 = blocks;
@@ -1042,21 +1072,21 @@ uint32_t place_blocks(std::vector<Inst> &ins, std::vector<uint32_t> &map)
         for (uint32_t j = 0; j < ins[r].nb; ++j) map.push_back(r);
         blocks += ins[r].nb;
     }
-    for (size_t o = 0; o < small.size(); o += 8) {
-        const size_t n = std::min<size_t>(8, small.size() - o);
-        uint32_t per = 0;
-        for (size_t k = 0; k < n; ++k) per = std::max(per, ins[small[o + k]].nb);
-        const size_t base = map.size();
-        map.resize(base + 8 * (size_t)per, NO_INSTANCE);
-        for (size_t k = 0; k < n; ++k) {
-            Inst &I = ins[small[o + k]];
-            I.block0 = blocks + (uint32_t)k;
-            I.bstride = 8;
-            for (uint32_t j = 0; j < I.nb; ++j) map[base + k + 8 * (size_t)j] = small[o + k];
-        }
-        blocks += 8 * per;
+    if (whole.empty()) return blocks;
+    uint32_t span = 0;
+    for (int x = 0; x < 8; ++x) span = std::max(span, used[x]);
+    const size_t base = map.size();
+    map.resize(base + 8 * (size_t)span, NO_INSTANCE);
+    uint32_t off[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (size_t q = 0; q < whole.size(); ++q) {
+        const uint32_t r = whole[q], x = xcd_of[q];
+        Inst &I = ins[r];
+        I.block0 = blocks + x + 8 * off[x];
+        I.bstride = 8;
+        for (uint32_t j = 0; j < I.nb; ++j) map[base + x + 8 * (size_t)(off[x] + j)] = r;
+        off[x] += I.nb;
     }
-    return blocks;
+    return blocks + 8 * span;
 }
 }  // namespace
 namespace {
@@ -1112,6 +1142,10 @@ void add_groups(kpm_ham *const *h, const std::vector<int> &ids, BatchLayout &L, 
             std::memset(&I, 0, sizeof(I));
             I.nb = p.nb;
             I.xcd = p.xcd;
+            I.nel = p.nel;
+            I.mode = p.mode;
+            I.nct = p.nct;
+            I.tiles = p.tiles;
             ins.push_back(I);
             L.order.push_back(i);
         }
@@ -1131,23 +1165,32 @@ bool batch_layout(kpm_ham *const *h, int32_t count, const int32_t *M, const int3
     L.plans.resize(count);
     L.prec = h[0] ? h[0]->prec : -1;
     L.map_words = 0;
-    std::vector<int> small;
-    std::vector<std::vector<int>> waves;
-    const uint64_t wave_bytes = (uint64_t)g_wave_mib << 20;
-    uint64_t wave_state = 0;
+    std::vector<int> small, rest;
     for (int i = 0; i < count; ++i) {
         if (!h[i] || h[i]->prec != L.prec) return false;
         if (!make_plan(h[i], M[i], R[i], vec, L.plans[i])) return false;
         if (L.plans[i].mode == MODE_SMALL) {
             small.push_back(i);
-            continue;
+        } else {
+            rest.push_back(i);
         }
-        if (waves.empty() || (wave_bytes && wave_state + L.plans[i].state > wave_bytes)) {
-            waves.emplace_back();
-            wave_state = 0;
+    }
+    // Waves: consecutive instances (argument order) while their state stays
+    // within wave_bytes.  (Dealing the instances out to the waves by size
+    // measured slower on batches of equal cubes, 834 vs 677 us per step for
+    // 2560 cubes of 16^3.)
+    const uint64_t wave_bytes = (uint64_t)g_wave_mib << 20;
+    std::vector<std::vector<int>> waves;
+    {
+        uint64_t ws = 0;
+        for (int i : rest) {
+            if (waves.empty() || (wave_bytes && ws + L.plans[i].state > wave_bytes)) {
+                waves.emplace_back();
+                ws = 0;
+            }
+            waves.back().push_back(i);
+            ws += L.plans[i].state;
         }
-        waves.back().push_back(i);
-        wave_state += L.plans[i].state;
     }
     add_groups(h, small, L, L.small);
     for (const std::vector<int> &w : waves) {
@@ -1666,12 +1709,13 @@ int32_t kpm_selftest_fastdiv(uint32_t d, const uint32_t *n, int32_t count)
     return 0;
 }
 
-// Host check of the block placement of one launch group: nb[i] blocks and the
-// XCD split flag of instance i.  Writes block0/bstride per instance and the
-// per-block map (up to map_cap entries); returns the grid size, or -1 if the
-// map does not fit.
-int64_t kpm_selftest_placement(const uint32_t *nb, const int32_t *xcd, int32_t count, uint32_t *block0,
-                               uint32_t *bstride, uint32_t *map_out, int64_t map_cap)
+// Host check of the block placement of one launch group: nb[i] blocks, the
+// XCD split flag xcd[i] (updated: 1 for instances the placement split) and,
+// optionally, units[i] work units of instance i (flat tiles; NULL: none).
+// Writes block0/bstride per instance and the per-block map (up to map_cap
+// entries); returns the grid size, or -1 if the map does not fit.
+int64_t kpm_selftest_placement(const uint32_t *nb, int32_t *xcd, const uint32_t *units, int32_t count,
+                               uint32_t *block0, uint32_t *bstride, uint32_t *map_out, int64_t map_cap)
 {
     if (!nb || !xcd || count < 1 || !block0 || !bstride || !map_out) return -1;
     std::vector<Inst> ins(count);
@@ -1679,6 +1723,8 @@ int64_t kpm_selftest_placement(const uint32_t *nb, const int32_t *xcd, int32_t c
         std::memset(&ins[i], 0, sizeof(Inst));
         ins[i].nb = nb[i];
         ins[i].xcd = xcd[i];
+        ins[i].mode = MODE_FLAT;
+        ins[i].tiles = units ? units[i] : 0;
     }
     std::vector<uint32_t> map;
     const uint32_t blocks = place_blocks(ins, map);
@@ -1686,6 +1732,7 @@ int64_t kpm_selftest_placement(const uint32_t *nb, const int32_t *xcd, int32_t c
     for (int32_t i = 0; i < count; ++i) {
         block0[i] = ins[i].block0;
         bstride[i] = ins[i].bstride;
+        xcd[i] = ins[i].xcd;
     }
     std::copy(map.begin(), map.end(), map_out);
     return blocks;

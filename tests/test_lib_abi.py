@@ -114,23 +114,27 @@ def test_no_cpu_fallback_when_library_missing(monkeypatch):
         kpm.lib()
 
 
+@pytest.mark.parametrize("split", [False, True])
 @pytest.mark.parametrize("case", range(6))
-def test_block_placement(L, case):
+def test_block_placement(L, case, split):
     """Multi-instance launches: every block of the grid maps to one block of one instance or is idle;
-    instances split per XCD start on a multiple of 8; every other instance has all its blocks on
-    one XCD (block b runs on XCD b mod 8)."""
+    instances split per XCD start on a multiple of 8; with at least 8 unsplit instances each of them
+    has all its blocks on one XCD (block b runs on XCD b mod 8) and the XCD loads are balanced (an
+    instance that would overload an XCD is split when it has >= 48 units)."""
     g = np.random.default_rng(case)
     n = [1, 3, 8, 9, 17, 256][case]
     nb = (g.integers(1, 40, n) * 8).astype(np.uint32)
     xcd = (g.random(n) < 0.3).astype(np.int32)
     if case == 0:
         xcd[:] = 0
+    xcd_in = xcd.copy()
+    units = (nb * 8).astype(np.uint32) if split else None
     b0 = np.zeros(n, np.uint32)
     bs = np.zeros(n, np.uint32)
     cap = int(nb.sum()) * 2 + 8 * int(nb.max())
     m = np.zeros(cap, np.uint32)
-    P = lambda a: a.ctypes.data_as(ctypes.c_void_p)
-    blocks = L.kpm_selftest_placement(P(nb), P(xcd), n, P(b0), P(bs), P(m), cap)
+    P = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+    blocks = L.kpm_selftest_placement(P(nb), P(xcd), P(units), n, P(b0), P(bs), P(m), cap)
     assert blocks > 0
     m = m[:blocks]
     seen = [set() for _ in range(n)]
@@ -143,13 +147,25 @@ def test_block_placement(L, case):
         j = off // bs[i]
         assert j < nb[i] and j not in seen[i]
         seen[i].add(j)
-    packed = int((xcd == 0).sum()) >= 8
+    packed = int((xcd_in == 0).sum()) >= 8
+    assert np.all(xcd[xcd_in == 1] == 1)
+    if not split:
+        assert np.array_equal(xcd, xcd_in)
+    load = np.zeros(8)
     for i in range(n):
         assert len(seen[i]) == nb[i]
         if xcd[i] or not packed:
             assert bs[i] == 1 and b0[i] % 8 == 0
+            if xcd[i] and not xcd_in[i]:
+                load += nb[i] / 8.0
         else:
             assert bs[i] == 8
-            assert len({(int(b0[i]) + 8 * j) % 8 for j in range(int(nb[i]))}) == 1
+            load[int(b0[i]) % 8] += nb[i]
+    if packed:
+        whole = nb[(xcd_in == 0)]
+        if split:    # within 10% of an even share, plus one share of a split instance
+            assert load.max() <= 1.10 * whole.sum() / 8.0 + 1e-9 + whole.max() / 8.0
+        else:        # greedy balance: XCD loads differ by at most one instance
+            assert load.max() - load.min() <= whole.max()
     idle = int((m == 0xFFFFFFFF).sum())
     assert idle <= 8 * int(nb.max()) + blocks // 4
