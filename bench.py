@@ -39,6 +39,9 @@ WORKLOAD_TEXT = {
 }
 
 
+CONFIG3_KERNEL = "k_step_march<float, OP_SPIN3> (multi-instance)"
+
+
 def bench_batched(args, log_fn):
     """Config 3: all 256 cubes solved together; a step = in-place operator preparation of every cube
     plus one replay of the captured graph of the batched solve (init, 256 multi-instance recursion
@@ -96,8 +99,8 @@ def bench_batched(args, log_fn):
         "config": {"workload": WORKLOAD_TEXT["config3"], "instances": len(lats), "N_total": N_tot, "M": M, "R": R,
                    "recursion": "complex64", "moments": "fp64"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_step_march<float, OP_SPIN3> (multi-instance)", "bytes_per_launch": bytes_step,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("config3", CONFIG3_KERNEL),
+                     "kernel": CONFIG3_KERNEL, "bytes_per_launch": bytes_step,
                      "avg_launch_us": step_us, "note": "whole batched solve time divided by its 256 launches"},
         "mu0_range": [min(m[0] for m in mus), max(m[0] for m in mus)],
     }
@@ -128,17 +131,65 @@ def kernel_source_digest():
     return h.hexdigest()[:16]
 
 
+TRAFFIC_PATH = os.path.join(ROOT, "profiles", "traffic.json")
+FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0     # calibrated on a plain device copy (measurement)
+
+
 def measured_traffic(workload, kernel):
-    """HBM bytes per launch of `kernel` from the committed counter record, or None when the
+    """HBM bytes per recursion step of `kernel` from the committed counter record, or None when the
     kernel source has changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
-        rec = json.load(open(path)).get(workload, {})
+        rec = json.load(open(TRAFFIC_PATH)).get(workload, {})
     except (OSError, ValueError):
         return None
     if rec.get("kernel") != kernel or rec.get("source_digest") != kernel_source_digest():
         return None
-    return rec["fetch_kib"] * 1024 * rec["fetch_factor"] + rec["write_kib"] * 1024 * rec["write_factor"]
+    return rec["traffic_bytes_per_step"]
+
+
+def _pmc_rows(root, counter):
+    import csv
+    rows = []
+    for dirpath, _, files in os.walk(root):
+        for f in files:
+            if f.endswith("counter_collection.csv"):
+                for r in csv.DictReader(open(os.path.join(dirpath, f))):
+                    if r["Counter_Name"] == counter:
+                        rows.append((r["Kernel_Name"], int(r["Grid_Size"]), float(r["Counter_Value"])))
+    return rows
+
+
+def record_traffic(workload, fetch_dir, write_dir, kernel, steps, commands):
+    """Write the HBM traffic of the recursion kernels of a profiled run into profiles/traffic.json:
+    FETCH_SIZE x 2 + WRITE_SIZE x 1 (KiB per dispatch) summed over every k_step_* dispatch of the
+    run and divided by its `steps` recursion steps (None: one step per dispatch); the 1 GiB copies
+    of --calib-copy are recorded beside it as the calibration evidence."""
+    fetch = _pmc_rows(fetch_dir, "FETCH_SIZE")
+    write = _pmc_rows(write_dir, "WRITE_SIZE")
+    step_f = [v for n, g, v in fetch if "k_step_" in n]
+    step_w = [v for n, g, v in write if "k_step_" in n]
+    # the 1 GiB copies of --calib-copy (1,048,576 KiB each way)
+    copy_f = [v for n, g, v in fetch if "copyBuffer" in n and v > 1e5]
+    copy_w = [v for n, g, v in write if "copyBuffer" in n and v > 1e5]
+    if not step_f or len(step_f) != len(step_w):
+        raise SystemExit(f"record_traffic: {len(step_f)} FETCH vs {len(step_w)} WRITE step dispatches")
+    steps = steps or len(step_f)
+    inst = sorted({n.split("(")[0] for n, g, v in fetch if "k_step_" in n})
+    traffic = (sum(step_f) * FETCH_FACTOR + sum(step_w) * WRITE_FACTOR) * 1024.0 / steps
+    try:
+        allrec = json.load(open(TRAFFIC_PATH))
+    except (OSError, ValueError):
+        allrec = {}
+    allrec[workload] = {
+        "kernel": kernel, "instantiations": inst, "source_digest": kernel_source_digest(),
+        "step_dispatches": len(step_f), "steps": steps,
+        "fetch_kib_total": sum(step_f), "write_kib_total": sum(step_w),
+        "fetch_factor": FETCH_FACTOR, "write_factor": WRITE_FACTOR,
+        "calibration_copy_dispatches": {"fetch_kib": copy_f, "write_kib": copy_w},
+        "traffic_bytes_per_step": traffic, "commands": commands}
+    with open(TRAFFIC_PATH, "w") as f:
+        json.dump(allrec, f, indent=1)
+    print(json.dumps(allrec[workload]))
 
 
 def pmc_summary(root):
@@ -259,12 +310,28 @@ def main():
                     help="first run a plain 1 GiB device copy three times (counter calibration under rocprofv3)")
     ap.add_argument("--pmc-summary", metavar="DIR",
                     help="print per-kernel averages of rocprofv3 --pmc CSV files found under DIR and exit")
+    ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/traffic.json for --workload from the FETCH_SIZE and WRITE_SIZE runs "
+                         "of one profiled solve (--steps 1 --warmup 0 --calib-copy) and exit")
     ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config4", "config5"],
                     help="config2 (the measured workload), config3 (256-cube batch), config4 (2D 2048^2, R=64, real FP32), config5 (serving record)")
     args = ap.parse_args()
 
     if args.pmc_summary:
         pmc_summary(args.pmc_summary)
+        return
+    if args.record_traffic:
+        import paper_1105_5481_amd.workloads as wl
+        cfg = getattr(wl, args.workload)()
+        kern = {"config2": "k_step_march<float, OP_SPIN3>", "config3": CONFIG3_KERNEL,
+                "config4": "k_step_march<float, OP_REAL2>"}[args.workload]
+        extra = {"config2": "--no-fp64 --no-cpu-baseline --no-serve ", "config4": "--no-fp64 --no-cpu-baseline --no-serve ",
+                 "config3": ""}[args.workload]
+        cmds = [f"rocprofv3 --pmc {c} --output-format csv -d <dir> -o p -- python3 bench.py --workload "
+                f"{args.workload} --steps 1 --warmup 0 {extra}--calib-copy" for c in ("FETCH_SIZE", "WRITE_SIZE")]
+        # a batched step is one dispatch per wave; a single solve's step is one dispatch
+        steps = cfg["M"] // 2 if args.workload == "config3" else None
+        record_traffic(args.workload, args.record_traffic[0], args.record_traffic[1], kern, steps, cmds)
         return
 
     if args.gpus != 1:
