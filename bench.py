@@ -234,7 +234,7 @@ def serving_leg(n_requests, logN_max, load, seed=1005):
                                                              r.lattice.dim if r.lattice.hop == wl.HOP_SPIN else 0)
     srv = Server(prec=kpm.F32, max_active=64, chunk=32)
     t0 = time.perf_counter()
-    res = srv.run(reqs([0.0] * n_requests), clock="chunks")
+    res = srv.run(reqs([0.0] * n_requests), clock="chunks", progress=log)
     makespan = time.perf_counter() - t0
     srv.close()
     assert all(r.status == "ok" for r in res)
@@ -248,12 +248,12 @@ def serving_leg(n_requests, logN_max, load, seed=1005):
         arrivals = np.cumsum(gaps / (ld * capacity))
         log(f"bench: load {ld}: trace over {arrivals[-1]:.2f} s")
         srv = Server(prec=kpm.F32, max_active=64, chunk=32)
-        served = srv.run(reqs(arrivals), clock="wall")
+        served = srv.run(reqs(arrivals), clock="wall", progress=log)
         conc = srv.max_concurrent
         srv.close()
         log(f"bench: load {ld}: FP32 served {latency_stats(served)}")
         srv = Server(prec=kpm.F64, max_active=1, chunk=64)
-        plain = srv.run(reqs(arrivals), clock="wall")
+        plain = srv.run(reqs(arrivals), clock="wall", progress=log)
         srv.close()
         svc64 = np.array([r.t_done - r.t_admit for r in plain if r.status == "ok"])
         cap64 = len(svc64) / svc64.sum()

@@ -246,13 +246,16 @@ class Server:
             self._inflight.popleft().synchronize()
         self._retire()
 
-    def run(self, requests: List[KPMRequest], clock: str = "wall", timeout: float = 3600.0) -> List[KPMResult]:
-        """Serve `requests` (arrival in seconds for clock="wall", in chunks for clock="chunks")."""
+    def run(self, requests: List[KPMRequest], clock: str = "wall", timeout: float = 3600.0, progress=None,
+            progress_every: float = 30.0) -> List[KPMResult]:
+        """Serve `requests` (arrival in seconds for clock="wall", in chunks for clock="chunks").
+        progress: optional callable receiving a status line every `progress_every` seconds."""
         self._clock_mode = clock
         self._clock0 = time.perf_counter()
         self._chunks = 0
         queue = deque(sorted(requests, key=lambda r: r.arrival))
         t_start = time.perf_counter()
+        t_note = t_start
         while queue or self.busy():
             now = self.now()
             while queue and queue[0].arrival <= now:
@@ -268,7 +271,12 @@ class Server:
                     time.sleep(max(0.0, min(queue[0].arrival - now, 0.01)))
                 else:
                     self._chunks += 1
-            if time.perf_counter() - t_start > timeout:
+            t = time.perf_counter()
+            if progress is not None and t - t_note >= progress_every:
+                t_note = t
+                progress(f"serve: {len(self.results)}/{len(requests)} done, {len(self.active)} active, "
+                         f"{len(self.pending) + len(queue)} waiting, {t - t_start:.0f} s")
+            if t - t_start > timeout:
                 raise KPMError("serving trace timed out")
         self.torch.cuda.synchronize()
         self._retire()
