@@ -138,6 +138,23 @@ kpm_status kpm_bounds_lanczos(kpm_ham *h, int32_t k, uint64_t seed, double pad, 
                               double clamp_hi, void *workspace_dev, size_t ws_bytes, double *out_dev,
                               void *stream);
 
+/* The dense-H variant of the recursion (the paper's own kernel design, Sec. III;
+ * its H_SIZE experiments of Sec. IV): H is a dense real symmetric D x D matrix
+ * (H_dev, row-major FP64, device memory), H~ = (H - b)/a is formed in the
+ * workspace ((H_ii - b)/a on the diagonal, H_ij/a off it), and each of the
+ * floor(M/2) steps computes V_{n+1} = 2 H~ V_n - V_{n-1} over all R vectors as
+ * one dense FP64 matrix product on the matrix cores, with the doubling-identity
+ * dot products fused into the same kernel; the moments are formed as in
+ * kpm_moments (mu_dev: device array of M doubles).  Real vectors only:
+ * vec = KPM_VEC_RADEMACHER or KPM_VEC_UNIT (KPM_ERR_UNSUPPORTED otherwise).
+ * H must be symmetric (not checked).  D <= 65536.  workspace_dev:
+ * kpm_dense_workspace_bytes(D, M, R) bytes, 256-byte aligned (the padded H~,
+ * two D x R vector blocks, partials and dots). */
+size_t kpm_dense_workspace_bytes(int64_t D, int32_t M, int32_t R);
+kpm_status kpm_dense_moments(const double *H_dev, int64_t D, double a, double b, int32_t M, int32_t R,
+                             int32_t vec, uint64_t seed, uint64_t instance, void *workspace_dev,
+                             size_t ws_bytes, double *mu_dev, void *stream);
+
 /* Build the scaled operator H~ = (H - b)/a (Eq. (tilde)) in device memory that
  * the handle owns (one hipMalloc, released by kpm_free), in the recursion
  * precision `prec`.  The FP64 values are formed as d_i = (H_ii - b)/a and

@@ -90,6 +90,8 @@ def lib():
         "kpm_graph_free": (None, [P]),
         "kpm_lanczos_workspace_bytes": (sz, [P, i32]),
         "kpm_green": (i32, [P, i32, i32, f64, i32, f64, f64, P, P, P, P]),
+        "kpm_dense_workspace_bytes": (sz, [i64, i32, i32]),
+        "kpm_dense_moments": (i32, [P, i64, f64, f64, i32, i32, i32, u64, u64, P, sz, P, P]),
         "kpm_bounds_lanczos": (i32, [P, i32, u64, f64, f64, f64, P, sz, P, P]),
     }
     for name, (res, args) in sigs.items():
@@ -466,6 +468,25 @@ def dos(mu, K: int, a: float, b: float, jackson: bool = True, stream=None):
     _check(lib().kpm_dos(mu.data_ptr(), M, 1 if jackson else 0, K, float(a), float(b), om.data_ptr(),
                          rho.data_ptr(), _stream(stream)), "kpm_dos")
     return om, rho
+
+
+def dense_moments(H, a: float, b: float, M: int, R: int, vec: int = VEC_RADEMACHER, seed: int = 0, instance: int = 0,
+                  stream=None, out=None, workspace=None):
+    """Moments of a dense real symmetric H (a D x D float64 device tensor, row-major) on the matrix
+    cores (kpm_dense_moments); returns a device tensor of M doubles."""
+    torch = _torch()
+    if H.dtype != torch.float64 or H.dim() != 2 or H.shape[0] != H.shape[1] or not H.is_contiguous():
+        raise KPMError("dense_moments needs a contiguous square float64 tensor")
+    D = H.shape[0]
+    nb = lib().kpm_dense_workspace_bytes(D, int(M), int(R))
+    if nb == 0:
+        raise KPMError(f"invalid dense solve shape D={D} M={M} R={R}")
+    ws = _workspace(nb, H.device, workspace)
+    mu = out if out is not None else torch.empty(int(M), dtype=torch.float64, device=H.device)
+    _check(lib().kpm_dense_moments(H.data_ptr(), D, float(a), float(b), int(M), int(R), int(vec), int(seed),
+                                   int(instance), ws.data_ptr(), nb, mu.data_ptr(), _stream(stream)),
+           "kpm_dense_moments")
+    return mu
 
 
 def green(mu, K: int, a: float, b: float, kernel: int = KERNEL_LORENTZ, lam: float = 4.0, stream=None):

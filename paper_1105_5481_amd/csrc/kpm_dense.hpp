@@ -1,0 +1,199 @@
+// The dense-H recursion (the paper's own kernel design, Sec. III and the
+// H_SIZE experiments of Sec. IV): H~ is a dense D x D real matrix and one
+// recursion step over the R vectors is the product H~ V_n (D x D times D x R),
+// a dense FP64 contraction, followed by V_{n+1} = 2 H~ V_n - V_{n-1} and the
+// two dot products of the doubling identities.
+//
+// Layout (all FP64, row-major, zero padded): H~ is Dp x Dp and every vector
+// block Dp x Rp, Dp and Rp multiples of 64, so padded rows and columns stay
+// exactly zero through the recursion and add nothing to the dots.
+//
+// One workgroup (4 waves) computes a 64 x 64 block of H~ V_n with the FP64
+// matrix instruction v_mfma_f64_16x16x4 (each wave a 32 x 32 quarter, 2 x 2
+// instruction tiles), staging 64 x 16 slices of H~ and 16 x 64 slices of V_n
+// through LDS, and finishes the block in registers: the recursion update,
+// the store of V_{n+1} over V_{n-1}, and the per-block double-double partial
+// sums of <V_{n+1}|V_{n+1}> and <V_{n+1}|V_n>.
+//
+// Lane layout of v_mfma_f64_16x16x4 (measured on gfx950): lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16] and receives D[4 v + l / 16][l % 16]
+// in element v of its 4-vector.
+#pragma once
+
+namespace kpm {
+
+constexpr int DN_TILE = 64;     // output block edge
+constexpr int DN_KT = 16;       // K slice staged per iteration
+typedef double dn_d4 __attribute__((ext_vector_type(4)));
+
+// H~ = (H - b I)/a into the padded Dp x Dp array (rows/cols >= D are zero);
+// the same operations as the CSR operator build: (H_ii - b)/a on the
+// diagonal, H_ij/a off it.
+__global__ __launch_bounds__(256) void k_dense_scale(const double *__restrict__ H, uint32_t D, uint32_t Dp, double a,
+                                                     double b, double *__restrict__ Ht)
+{
+    const uint64_t e = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (uint64_t)Dp * Dp) return;
+    const uint32_t i = (uint32_t)(e / Dp), j = (uint32_t)(e % Dp);
+    double v = 0.0;
+    if (i < D && j < D) {
+        const double h = H[(uint64_t)i * D + j];
+        v = (i == j) ? (h - b) / a : h / a;
+    }
+    Ht[e] = v;
+}
+
+// V_0 = xi (R real start vectors of kind vec, column r = vector r) over the
+// output tiles of the step kernel, with the partials of <V_0|V_0> (slot 0).
+__global__ __launch_bounds__(256) void k_dense_init(uint32_t D, uint32_t Dp, uint32_t R, uint32_t Rp, int vec,
+                                                    uint64_t seed, uint64_t instance, double *__restrict__ V,
+                                                    double *__restrict__ part)
+{
+    const uint32_t tiles_r = Rp / DN_TILE;
+    const uint32_t i0 = (blockIdx.x / tiles_r) * DN_TILE, r0 = (blockIdx.x % tiles_r) * DN_TILE;
+    double s = 0.0, c = 0.0;
+    for (uint32_t q = threadIdx.x; q < DN_TILE * DN_TILE; q += 256) {
+        const uint32_t i = i0 + q / DN_TILE, r = r0 + q % DN_TILE;
+        double re = 0.0, im = 0.0;
+        if (i < D && r < R) {
+            uint64_t w[4] = {0, 0, 0, 0};
+            if (vec != VEC_UNIT) start_words(seed, instance, i, r / 4, w);
+            start_value(vec, w[r & 3], instance, D, i, r, re, im);
+        }
+        V[(uint64_t)i * Rp + r] = re;
+        dot2_acc(s, c, re, re);
+    }
+    block_reduce_store<true>(s, c, 0.0, 0.0, part + (size_t)blockIdx.x * 4);
+}
+
+// One recursion step: next = H~ cur (FIRST) or 2 H~ cur - next, and the
+// partials of <next|next>, <next|cur> for the dots index of this step.
+template <bool FIRST>
+__global__ __launch_bounds__(256) void k_dense_step(const double *__restrict__ Ht, const double *__restrict__ cur,
+                                                    double *__restrict__ next, uint32_t Dp, uint32_t Rp,
+                                                    double *__restrict__ part)
+{
+    __shared__ double As[DN_TILE][DN_KT + 1];
+    __shared__ double Bs[DN_KT][DN_TILE + 2];
+    const uint32_t tiles_r = Rp / DN_TILE;
+    const uint32_t i0 = (blockIdx.x / tiles_r) * DN_TILE, r0 = (blockIdx.x % tiles_r) * DN_TILE;
+    const int t = threadIdx.x, l = t & 63, w = t >> 6;
+    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;     // this wave's 32 x 32 quarter
+    const int lr = l & 15, lk = l >> 4;
+    dn_d4 acc[2][2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) acc[p][q] = dn_d4{0.0, 0.0, 0.0, 0.0};
+    for (uint32_t k0 = 0; k0 < Dp; k0 += DN_KT) {
+        // stage H~[i0:i0+64, k0:k0+16] and cur[k0:k0+16, r0:r0+64] (1024 values each)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int q = t + 256 * u;
+            As[q >> 4][q & 15] = Ht[(uint64_t)(i0 + (q >> 4)) * Dp + k0 + (q & 15)];
+            Bs[q >> 6][q & 63] = cur[(uint64_t)(k0 + (q >> 6)) * Rp + r0 + (q & 63)];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < DN_KT; kk += 4) {
+            double av[2], bv[2];
+#pragma unroll
+            for (int p = 0; p < 2; ++p) av[p] = As[wr + 16 * p + lr][kk + lk];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) bv[q] = Bs[kk + lk][wc + 16 * q + lr];
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+#pragma unroll
+                for (int q = 0; q < 2; ++q) acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[p], bv[q], acc[p][q], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    double s0 = 0.0, c0 = 0.0, s1 = 0.0, c1 = 0.0;
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const uint32_t i = i0 + wr + 16 * p + 4 * v + lk;
+                const uint32_t r = r0 + wc + 16 * q + lr;
+                const uint64_t o = (uint64_t)i * Rp + r;
+                double out = acc[p][q][v];
+                if (!FIRST) out = 2.0 * out - next[o];
+                next[o] = out;
+                dot2_acc(s0, c0, out, out);
+                dot2_acc(s1, c1, out, cur[o]);
+            }
+    block_reduce_store<true>(s0, c0, s1, c1, part + (size_t)blockIdx.x * 4);
+}
+
+// ---------------------------------------------------------------------------
+// small H~ (D <= 128): the whole recursion on chip, one launch
+// ---------------------------------------------------------------------------
+// H~ lives in LDS (Dp x Dp, Dp = 16 NW) and each block owns a 16-column slab
+// of the vectors for all steps: wave w computes rows 16w .. 16w + 15 of
+// H~ V_n with Dp/4 matrix instructions; the 4 results a lane receives
+// (rows 16w + 4v + l/16, column l % 16) are exactly the B-operand values the
+// same lane supplies for those rows in the next step, so r_{n-1}, r_n and
+// r_{n+1} stay in registers and only the slab of r_n is shared through LDS.
+// H~ must be symmetric: the A operand H~[i][k] is read as H~[k][i], which
+// keeps the LDS reads of a wave on consecutive addresses.  The per-step dot
+// partials of each block go to slot n + 1 of `part` ([K + 1][blocks][4]).
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void k_dense_resident(const double *__restrict__ Ht, uint32_t D, uint32_t R,
+                                                            int vec, uint64_t seed, uint64_t instance, int32_t K,
+                                                            double *__restrict__ part)
+{
+    extern __shared__ double lds[];
+    constexpr uint32_t Dp = 16 * NW;
+    constexpr int NT = 64 * NW;
+    double *Hs = lds;              // Dp x Dp
+    double *Vs = lds + Dp * Dp;    // Dp x 16
+    const int t = threadIdx.x, l = t & 63, w = t >> 6;
+    const int lr = l & 15, lk = l >> 4;
+    const uint32_t nblk = gridDim.x;
+    const uint32_t col = blockIdx.x * 16 + lr;
+    for (uint32_t q = t; q < Dp * Dp; q += NT) Hs[q] = Ht[q];
+    double cur[4], prev[4] = {0.0, 0.0, 0.0, 0.0};
+    double s0 = 0.0, e0 = 0.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const uint32_t i = 16 * w + 4 * v + lk;
+        double re = 0.0, im = 0.0;
+        if (i < D && col < R) {
+            uint64_t wd[4] = {0, 0, 0, 0};
+            if (vec != VEC_UNIT) start_words(seed, instance, i, col / 4, wd);
+            start_value(vec, wd[col & 3], instance, D, i, col, re, im);
+        }
+        cur[v] = re;
+        Vs[i * 16 + lr] = re;
+        dot2_acc(s0, e0, re, re);
+    }
+    block_reduce_store<true, NT>(s0, e0, 0.0, 0.0, part + (size_t)blockIdx.x * 4);
+    __syncthreads();
+    for (int32_t n = 0; n < K; ++n) {
+        dn_d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+        for (uint32_t s = 0; s < Dp / 4; s += 2) {
+            const uint32_t k0 = 4 * s + lk, k1 = 4 * (s + 1) + lk;
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(Hs[k0 * Dp + 16 * w + lr], Vs[k0 * 16 + lr], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(Hs[k1 * Dp + 16 * w + lr], Vs[k1 * 16 + lr], acc1, 0, 0, 0);
+        }
+        __syncthreads();   // every wave has read the slab of r_n
+        double x0 = 0.0, y0 = 0.0, x1 = 0.0, y1 = 0.0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            double out = acc0[v] + acc1[v];
+            if (n > 0) out = 2.0 * out - prev[v];
+            dot2_acc(x0, y0, out, out);
+            dot2_acc(x1, y1, out, cur[v]);
+            prev[v] = cur[v];
+            cur[v] = out;
+            Vs[(16 * w + 4 * v + lk) * 16 + lr] = out;
+        }
+        block_reduce_store<true, NT>(x0, y0, x1, y1, part + ((size_t)(n + 1) * nblk + blockIdx.x) * 4);
+        __syncthreads();   // the slab of r_{n+1} is complete
+    }
+}
+
+}  // namespace kpm

@@ -12,6 +12,7 @@
 #include "kpm.h"
 #include "kpm_kernels.hpp"
 #include "kpm_lanczos.hpp"
+#include "kpm_dense.hpp"
 
 using namespace kpm;
 
@@ -1603,6 +1604,124 @@ kpm_status kpm_bounds_lanczos(kpm_ham *h, int32_t k, uint64_t seed, double pad, 
                            out_dev);
         e = check_launch();
     }
+    return e;
+}
+
+// ---------------------------------------------------------------------------
+// dense-H recursion
+// ---------------------------------------------------------------------------
+extern "C++" {
+namespace {
+constexpr int64_t DENSE_RESIDENT_MAX = 128;   // H~ (FP64) and one vector slab fit one CU's LDS
+struct DenseLayout {
+    bool resident;
+    uint32_t Dp, Rp, tiles;
+    int32_t K, P_slots;
+    size_t ht_off, v0_off, v1_off, part_off, dots_off, total;
+};
+bool dense_layout(int64_t D, int32_t M, int32_t R, DenseLayout &L)
+{
+    if (D < 1 || D > 65536 || M < 1 || R < 1 || R > (1 << 20)) return false;
+    L.resident = g_small && D <= DENSE_RESIDENT_MAX;
+    const uint32_t q = L.resident ? 16 : DN_TILE;
+    L.Dp = (uint32_t)((D + q - 1) / q * q);
+    L.Rp = (uint32_t)((R + q - 1) / q * q);
+    if ((uint64_t)L.Dp * L.Rp >= (1ull << 40)) return false;
+    L.tiles = L.resident ? L.Rp / 16 : (L.Dp / DN_TILE) * (L.Rp / DN_TILE);
+    L.K = M / 2;
+    L.P_slots = L.resident ? L.K + 1 : std::min(L.K + 1, PSLOTS_MAX);
+    const size_t vbytes = L.resident ? 0 : align256((size_t)L.Dp * L.Rp * 8);
+    L.ht_off = align256(sizeof(Inst));
+    L.v0_off = L.ht_off + align256((size_t)L.Dp * L.Dp * 8);
+    L.v1_off = L.v0_off + vbytes;
+    L.part_off = L.v1_off + vbytes;
+    L.dots_off = L.part_off + align256((size_t)L.P_slots * L.tiles * 4 * 8);
+    L.total = L.dots_off + align256((size_t)(L.K + 1) * 4 * 8);
+    return true;
+}
+}  // namespace
+}  // extern "C++"
+
+size_t kpm_dense_workspace_bytes(int64_t D, int32_t M, int32_t R)
+{
+    DenseLayout L;
+    return dense_layout(D, M, R, L) ? L.total : 0;
+}
+
+kpm_status kpm_dense_moments(const double *H_dev, int64_t D, double a, double b, int32_t M, int32_t R, int32_t vec,
+                             uint64_t seed, uint64_t instance, void *ws, size_t ws_bytes, double *mu_dev, void *stream)
+{
+    DenseLayout L;
+    if (!H_dev || !mu_dev || !(a > 0.0) || !std::isfinite(b) || !dense_layout(D, M, R, L)) return KPM_ERR_INVALID_ARG;
+    if (vec != KPM_VEC_RADEMACHER && vec != KPM_VEC_UNIT) return KPM_ERR_UNSUPPORTED;   // real vectors only
+    if (!ws || ((uintptr_t)ws & 255) || ws_bytes < L.total) return KPM_ERR_WORKSPACE;
+    if (ensure_phase_table() != KPM_OK) return KPM_ERR_DEVICE;
+    hipStream_t st = S(stream);
+    char *base = (char *)ws;
+    double *Ht = (double *)(base + L.ht_off);
+    double *V[2] = {(double *)(base + L.v0_off), (double *)(base + L.v1_off)};
+    double *part = (double *)(base + L.part_off);
+    Inst I;
+    std::memset(&I, 0, sizeof(I));
+    I.mode = MODE_FLAT;
+    I.tiles = L.tiles;
+    I.pslots = L.P_slots;
+    I.K = L.K;
+    I.M = M;
+    I.R = R;
+    I.vec = vec;
+    I.norm = (vec == KPM_VEC_UNIT) ? (double)R : (double)D * (double)R;
+    I.partial = part;
+    I.dots = (double *)(base + L.dots_off);
+    I.mu = mu_dev;
+    Inst *tab = (Inst *)base;
+    kpm_status e = upload(tab, &I, sizeof(Inst), st);
+    if (e == KPM_OK) {
+        const uint64_t n2 = (uint64_t)L.Dp * L.Dp;
+        hipLaunchKernelGGL(k_dense_scale, dim3((uint32_t)((n2 + 255) / 256)), dim3(256), 0, st, H_dev, (uint32_t)D, L.Dp,
+                           a, b, Ht);
+        e = check_launch();
+    }
+    if (e == KPM_OK && L.resident) {
+        typedef void (*res_fn)(const double *, uint32_t, uint32_t, int, uint64_t, uint64_t, int32_t, double *);
+        static const res_fn fns[8] = {k_dense_resident<1>, k_dense_resident<2>, k_dense_resident<3>,
+                                      k_dense_resident<4>, k_dense_resident<5>, k_dense_resident<6>,
+                                      k_dense_resident<7>, k_dense_resident<8>};
+        const int nw = (int)(L.Dp / 16);
+        const size_t lds = ((size_t)L.Dp * L.Dp + (size_t)L.Dp * 16) * 8;
+        if (hipFuncSetAttribute((const void *)fns[nw - 1], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+            hipSuccess)
+            return KPM_ERR_DEVICE;
+        hipLaunchKernelGGL(fns[nw - 1], dim3(L.tiles), dim3(64 * nw), lds, st, Ht, (uint32_t)D, (uint32_t)R, vec, seed,
+                           instance, L.K, part);
+        e = check_launch();
+        if (e == KPM_OK) e = launch_reduce(tab, 1, -1, L.K + 1, st);
+        if (e == KPM_OK) e = launch_moments(tab, 1, M, st);
+        return e;
+    }
+    if (e == KPM_OK) {
+        hipLaunchKernelGGL(k_dense_init, dim3(L.tiles), dim3(256), 0, st, (uint32_t)D, L.Dp, (uint32_t)R, L.Rp, vec, seed,
+                           instance, V[0], part);
+        e = check_launch();
+    }
+    int32_t written = 1, reduced = 0;
+    for (int32_t n = 0; n < L.K && e == KPM_OK; ++n) {
+        if (written - reduced >= L.P_slots) {
+            e = launch_reduce(tab, 1, reduced - 1, written - reduced, st);
+            reduced = written;
+            if (e != KPM_OK) break;
+        }
+        double *pslot = part + (size_t)((n + 1) % L.P_slots) * L.tiles * 4;
+        if (n == 0)
+            hipLaunchKernelGGL(k_dense_step<true>, dim3(L.tiles), dim3(256), 0, st, Ht, V[0], V[1], L.Dp, L.Rp, pslot);
+        else
+            hipLaunchKernelGGL(k_dense_step<false>, dim3(L.tiles), dim3(256), 0, st, Ht, V[n & 1], V[(n + 1) & 1], L.Dp,
+                               L.Rp, pslot);
+        e = check_launch();
+        written += 1;
+    }
+    if (e == KPM_OK) e = launch_reduce(tab, 1, reduced - 1, written - reduced, st);
+    if (e == KPM_OK) e = launch_moments(tab, 1, M, st);
     return e;
 }
 
