@@ -40,6 +40,80 @@ WORKLOAD_TEXT = {
 
 
 CONFIG3_KERNEL = "k_step_march<float, OP_SPIN3> (multi-instance)"
+FP64_MFMA_PEAK_TFLOPS = 78.6
+
+
+def bench_dense(args, log_fn):
+    """The dense-H recursion on the matrix cores at the shapes of the paper's dense experiments
+    (R x S = 1792 vectors): E1 (the 10^3 lattice as a dense matrix, M=1024), E3 (D=128, M=2048),
+    E4 (D=4096, M=128).  A step = one whole solve (scale, start vectors, floor(M/2) fused
+    product steps, reductions, moments); the bench line is E4's."""
+    import numpy as np
+    import torch
+    import paper_1105_5481_amd as kpm
+    from paper_1105_5481_amd import workloads as wl
+    cfg = wl.dense_workloads()
+    R, vec, seed = cfg["R"], cfg["vec"], cfg["seed"]
+    shapes = {}
+    line = None
+    for name, (kind, D, M) in cfg["shapes"].items():
+        if kind == "lattice":
+            Hn = wl.csr_to_dense(wl.lattice_to_csr(wl.cubic_lattice(10, t=1.0, W=0.0, seed=seed)))
+        else:
+            Hn = wl.dense_symmetric(D, seed)
+        off = np.abs(Hn).sum(axis=1) - np.abs(np.diag(Hn))
+        a, b = kpm.scale_from_bounds(float((np.diag(Hn) - off).min()), float((np.diag(Hn) + off).max()), 0.01)
+        H = torch.tensor(Hn, device="cuda")
+        mu = torch.empty(M, dtype=torch.float64, device="cuda")
+        nb = kpm.lib().kpm_dense_workspace_bytes(D, M, R)
+        ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        run = lambda: kpm.dense_moments(H, a, b, M, R, vec, seed, 0, out=mu, workspace=ws)
+        for _ in range(max(1, args.warmup)):
+            run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record()
+        for _ in range(args.steps):
+            run()
+        e1.record()
+        e1.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        gpu = e0.elapsed_time(e1) * 1e-3 / args.steps
+        K = M // 2
+        flops = 2.0 * D * D * R * K
+        shapes[name] = {"D": D, "M": M, "R": R, "ms_per_solve": dt * 1e3, "updates_per_s": D * M * R / dt,
+                        "TFLOP_per_s": flops / gpu / 1e12, "mu0": float(mu[0])}
+        log_fn(f"bench: dense {name}: {dt * 1e3:.2f} ms per solve, {flops / gpu / 1e12:.1f} TFLOP/s")
+        if name.startswith("E4"):
+            line = (D, M, dt, gpu, flops, Hn, a, b)
+    D, M, dt, gpu, flops, Hn, a, b = line
+    achieved = flops / gpu / 1e12
+    out = {
+        "metric": METRIC, "value": D * M * R / dt, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "dense real symmetric H (Gaussian orthogonal ensemble), D=4096, R=1792 +-1 vectors, "
+                               "M=128 moments, FP64 on the matrix cores (the paper's largest H_SIZE shape)",
+                   "D": D, "M": M, "R": R},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": None, "kernel": "k_dense_step",
+                     "flops_per_launch": 2.0 * D * D * R,
+                     "note": "whole solve time (scale, init, reductions included) charged to its M/2 products"},
+        "shapes": shapes,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build()
+        c = wl.CSR(n=D, row_ptr=(np.arange(D + 1) * D).astype(np.int64),
+                   col=np.tile(np.arange(D), D).astype(np.int32), val_re=np.ascontiguousarray(Hn.reshape(-1)))
+        Ms, Rs = 16, 14
+        t0 = time.perf_counter()
+        oracle.moments_csr(c.row_ptr, c.col, c.val_re, None, a, b, Ms, Rs, vec, seed, 0)
+        dc = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": D * Ms * Rs / dc, "unit": UNIT, "cores": oracle.max_threads(), "kind": "oracle",
+                               "sample": f"the D={D} matrix as CSR, M={Ms} moments, R={Rs} vectors ({dc:.1f} s)"}
+    return out
 
 
 def bench_batched(args, log_fn):
@@ -313,7 +387,7 @@ def main():
     ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/traffic.json for --workload from the FETCH_SIZE and WRITE_SIZE runs "
                          "of one profiled solve (--steps 1 --warmup 0 --calib-copy) and exit")
-    ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config4", "config5"],
+    ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config4", "config5", "dense"],
                     help="config2 (the measured workload), config3 (256-cube batch), config4 (2D 2048^2, R=64, real FP32), config5 (serving record)")
     args = ap.parse_args()
 
@@ -372,6 +446,9 @@ def main():
         return
     if args.workload == "config3":
         print(json.dumps(bench_batched(args, log)), flush=True)
+        return
+    if args.workload == "dense":
+        print(json.dumps(bench_dense(args, log)), flush=True)
         return
     cfg = wl.config2() if args.workload == "config2" else wl.config4()
     lat, M, R, vec, seed = cfg["lattice"], cfg["M"], cfg["R"], cfg["vec"], cfg["seed"]

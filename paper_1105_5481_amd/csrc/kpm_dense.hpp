@@ -85,15 +85,32 @@ __global__ __launch_bounds__(256) void k_dense_step(const double *__restrict__ H
     for (int p = 0; p < 2; ++p)
 #pragma unroll
         for (int q = 0; q < 2; ++q) acc[p][q] = dn_d4{0.0, 0.0, 0.0, 0.0};
+    // the slices H~[i0:i0+64, k0:k0+16] and cur[k0:k0+16, r0:r0+64] (1024 values
+    // each, 4 per thread); the next slice is loaded into registers while the
+    // matrix instructions work on the current one in LDS
+    double ra[4], rb[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int q = t + 256 * u;
+        ra[u] = Ht[(uint64_t)(i0 + (q >> 4)) * Dp + (q & 15)];
+        rb[u] = cur[(uint64_t)(q >> 6) * Rp + r0 + (q & 63)];
+    }
     for (uint32_t k0 = 0; k0 < Dp; k0 += DN_KT) {
-        // stage H~[i0:i0+64, k0:k0+16] and cur[k0:k0+16, r0:r0+64] (1024 values each)
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int q = t + 256 * u;
-            As[q >> 4][q & 15] = Ht[(uint64_t)(i0 + (q >> 4)) * Dp + k0 + (q & 15)];
-            Bs[q >> 6][q & 63] = cur[(uint64_t)(k0 + (q >> 6)) * Rp + r0 + (q & 63)];
+            As[q >> 4][q & 15] = ra[u];
+            Bs[q >> 6][q & 63] = rb[u];
         }
         __syncthreads();
+        if (k0 + DN_KT < Dp) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int q = t + 256 * u;
+                ra[u] = Ht[(uint64_t)(i0 + (q >> 4)) * Dp + k0 + DN_KT + (q & 15)];
+                rb[u] = cur[(uint64_t)(k0 + DN_KT + (q >> 6)) * Rp + r0 + (q & 63)];
+            }
+        }
 #pragma unroll
         for (int kk = 0; kk < DN_KT; kk += 4) {
             double av[2], bv[2];

@@ -16,7 +16,7 @@ from typing import List, Optional, Tuple
 
 import numpy as np
 
-TAG_DISORDER, TAG_SPINS, TAG_REDRAW, TAG_VECTORS, TAG_SIZE, TAG_ARRIVAL, TAG_REQUEST = 1, 2, 3, 4, 5, 6, 7
+TAG_DISORDER, TAG_SPINS, TAG_REDRAW, TAG_VECTORS, TAG_SIZE, TAG_ARRIVAL, TAG_REQUEST, TAG_DENSE = 1, 2, 3, 4, 5, 6, 7, 8
 
 HOP_REAL, HOP_SPIN = 0, 1
 VEC_RADEMACHER, VEC_PHASE, VEC_UNIT = 0, 1, 2
@@ -219,6 +219,35 @@ def config3(count: int = 256, Lmin: int = 16, Lmax: int = 48) -> dict:
         lats.append(spin_cubic_lattice(L, t=1.0, theta=th, phi=ph))
     return dict(lattices=lats, M=512, R=16, vec=VEC_PHASE, seed=seed,
                 name=f"batched_spin_cubic_{count}x_L{Lmin}-{Lmax}_M512_R16")
+
+
+def csr_to_dense(c: CSR) -> np.ndarray:
+    """The real part of a CSR matrix as a dense row-major float64 array (entries with equal
+    (row, col) summed)."""
+    H = np.zeros((c.n, c.n))
+    rows = np.repeat(np.arange(c.n), np.diff(c.row_ptr))
+    np.add.at(H, (rows, c.col), c.val_re)
+    return H
+
+
+def dense_symmetric(D: int, seed: int) -> np.ndarray:
+    """A dense real symmetric D x D matrix with independent N(0, 1/(2D)) entries above the diagonal
+    and N(0, 1/D) on it (the Gaussian orthogonal ensemble, spectrum ~ [-2, 2]), row-major float64."""
+    g = rng(seed, TAG_DENSE)
+    X = g.normal(size=(D, D)) / np.sqrt(2.0 * D)
+    return np.ascontiguousarray(X + X.T)
+
+
+def dense_workloads() -> dict:
+    """The shapes of the paper's dense-H experiments (Sec. IV): R x S = 1792 vectors (+-1).
+    E1: the 10x10x10 cubic lattice with zero diagonal and -1 hopping as a dense matrix (D = 1000),
+    M = 1024; E3: D = 128, M = 2048; E4: D = 4096 (the largest H_SIZE), M = 128.  E3 and E4 use
+    dense_symmetric matrices (the paper does not specify its matrices)."""
+    seed = 1006
+    return dict(R=1792, vec=VEC_RADEMACHER, seed=seed,
+                shapes={"E1_lattice_D1000_M1024": ("lattice", 1000, 1024),
+                        "E3_D128_M2048": ("random", 128, 2048),
+                        "E4_D4096_M128": ("random", 4096, 128)})
 
 
 def config4() -> dict:
