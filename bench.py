@@ -236,8 +236,8 @@ def _pmc_rows(root, counter):
 def record_traffic(workload, fetch_dir, write_dir, kernel, steps, commands):
     """Write the HBM traffic of the recursion kernels of a profiled run into profiles/traffic.json:
     FETCH_SIZE x 2 + WRITE_SIZE x 1 (KiB per dispatch) summed over every k_step_* dispatch of the
-    run and divided by its `steps` recursion steps (None: one step per dispatch); the 1 GiB copies
-    of --calib-copy are recorded beside it as the calibration evidence."""
+    run and divided by its `steps` recursion steps; the 1 GiB copies of --calib-copy are recorded
+    beside it as the calibration evidence."""
     fetch = _pmc_rows(fetch_dir, "FETCH_SIZE")
     write = _pmc_rows(write_dir, "WRITE_SIZE")
     step_f = [v for n, g, v in fetch if "k_step_" in n]
@@ -247,7 +247,6 @@ def record_traffic(workload, fetch_dir, write_dir, kernel, steps, commands):
     copy_w = [v for n, g, v in write if "copyBuffer" in n and v > 1e5]
     if not step_f or len(step_f) != len(step_w):
         raise SystemExit(f"record_traffic: {len(step_f)} FETCH vs {len(step_w)} WRITE step dispatches")
-    steps = steps or len(step_f)
     inst = sorted({n.split("(")[0] for n, g, v in fetch if "k_step_" in n})
     traffic = (sum(step_f) * FETCH_FACTOR + sum(step_w) * WRITE_FACTOR) * 1024.0 / steps
     try:
@@ -380,6 +379,7 @@ def main():
     ap.add_argument("--alternate", type=int, default=-1)
     ap.add_argument("--streaming", type=int, default=-1)
     ap.add_argument("--wave-mib", type=int, default=-1, help="batched solves: MiB of state per wave, 0 = one wave")
+    ap.add_argument("--tblock", type=int, default=-1, help="2D real lattices: 1 two steps per pass, 0 one step")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain 1 GiB device copy three times (counter calibration under rocprofv3)")
     ap.add_argument("--pmc-summary", metavar="DIR",
@@ -398,13 +398,15 @@ def main():
         import paper_1105_5481_amd.workloads as wl
         cfg = getattr(wl, args.workload)()
         kern = {"config2": "k_step_march<float, OP_SPIN3>", "config3": CONFIG3_KERNEL,
-                "config4": "k_step_march<float, OP_REAL2>"}[args.workload]
+                "config4": "k_step_tb<float> (two steps per launch)"}[args.workload]
         extra = {"config2": "--no-fp64 --no-cpu-baseline --no-serve ", "config4": "--no-fp64 --no-cpu-baseline --no-serve ",
                  "config3": ""}[args.workload]
         cmds = [f"rocprofv3 --pmc {c} --output-format csv -d <dir> -o p -- python3 bench.py --workload "
                 f"{args.workload} --steps 1 --warmup 0 {extra}--calib-copy" for c in ("FETCH_SIZE", "WRITE_SIZE")]
-        # a batched step is one dispatch per wave; a single solve's step is one dispatch
-        steps = cfg["M"] // 2 if args.workload == "config3" else None
+        # recursion steps of the profiled run: M/2 per solve, and every solve (a batched one too)
+        # ends with one k_moments dispatch
+        solves = sum(1 for n, g, v in _pmc_rows(args.record_traffic[0], "FETCH_SIZE") if "k_moments" in n)
+        steps = cfg["M"] // 2 * solves
         record_traffic(args.workload, args.record_traffic[0], args.record_traffic[1], kern, steps, cmds)
         return
 
@@ -433,7 +435,8 @@ def main():
                    xcd_split=None if args.xcd_split < 0 else args.xcd_split,
                    alternate=None if args.alternate < 0 else args.alternate,
                    streaming=None if args.streaming < 0 else args.streaming,
-                   wave_mib=None if args.wave_mib < 0 else args.wave_mib)
+                   wave_mib=None if args.wave_mib < 0 else args.wave_mib,
+                   tblock=None if args.tblock < 0 else args.tblock)
     dev = "cuda"
     stream = torch.cuda.current_stream()
 
@@ -475,12 +478,15 @@ def main():
     sp = ctypes.c_void_p(stream.cuda_stream)
     K = M // 2
 
+    solve_mode = {}
+
     def run_step(state, instance, ev=None):
         h, ws, nbytes, mu, om, rho = state
         kpm._check(L.kpm_update(h.handle, ctypes.byref(desc), a, b, sp), "kpm_update")            # a0
         s = ctypes.c_void_p()
         kpm._check(L.kpm_solve_begin(h.handle, M, R, vec, seed, instance, ws.data_ptr(), nbytes, sp,
                                      ctypes.byref(s)), "kpm_solve_begin")                         # a1
+        solve_mode[h.prec] = L.kpm_solve_mode(s)
         if ev is not None:
             ev[0].record(stream)
         rem = ctypes.c_int32()
@@ -511,11 +517,14 @@ def main():
     ms_per_step = dt32 / args.steps * 1e3
     updates = float(N) * M * R
     value = updates / (dt32 / args.steps)
-    nrec = K - 1
-    step_us = rec32 * 1e3 / nrec
+    tblocked = solve_mode.get(kpm.F32) == 3
+    nrec = K if tblocked else K - 1          # begin runs step 0 except with two steps per launch
+    step_us = rec32 * 1e3 / nrec             # per recursion step
     bonds = lat.dim if lat.hop == wl.HOP_SPIN else 0
     mode = "march" if kpm.get_launch()["march"] else "flat"
     kernel_name = "k_step_%s<float, %s>" % (mode, "OP_SPIN3" if bonds else "OP_REAL2")
+    if tblocked:
+        kernel_name = "k_step_tb<float> (two steps per launch)"
     bytes_step = algorithmic_bytes_per_step(N, R, cplx, 4, s32[0].b != 0.0 or lat.onsite is not None, bonds)
     achieved = bytes_step / (step_us * 1e-6) / 1e9
     # same start vectors for the c64 / c128 comparison
@@ -535,6 +544,9 @@ def main():
                      "bytes_per_launch": bytes_step,
                      "avg_launch_us": step_us},
     }
+    if tblocked:
+        out["roofline"]["note"] = ("two recursion steps per launch: bytes_per_launch and avg_launch_us are per step "
+                                   "(the method's 3 vector streams per step; the kernel moves about 2)")
 
     if not args.no_fp64:
         s64 = make_solver(kpm.F64)

@@ -103,6 +103,10 @@ typedef struct kpm_solve kpm_solve; /* opaque: one solve whose state lives in a 
 /* Human-readable name of a status code (static string). */
 const char *kpm_status_string(kpm_status st);
 
+/* Name of the last HIP runtime error a call of this thread ran into (behind
+ * KPM_ERR_DEVICE and allocation failures); "no error" if none. */
+const char *kpm_last_hip_error(void);
+
 /* Gershgorin bounds of H (Sec. II-A, below Eq. (tilde)):
  *   E_lo = min_i (Re H_ii - sum_{j!=i} |H_ij|),  E_hi = max_i (Re H_ii + sum_{j!=i} |H_ij|),
  * computed in FP64 on the device.  A lattice neighbour slot that wraps onto the
@@ -209,6 +213,10 @@ kpm_status kpm_solve_begin(kpm_ham *h, int32_t M, int32_t R, int32_t vec, uint64
 kpm_status kpm_solve_advance(kpm_solve *s, int32_t max_steps, void *stream, int32_t *remaining);
 kpm_status kpm_solve_finish(kpm_solve *s, double *mu_dev, void *stream);
 void kpm_solve_free(kpm_solve *s);
+/* How the solve's recursion runs: 0 flat kernels (one step per launch), 1 march
+ * kernels (one step per launch), 2 whole recursion in one workgroup (done at
+ * begin), 3 temporal blocking (two steps per launch); -1 for NULL. */
+int32_t kpm_solve_mode(const kpm_solve *s);
 
 /* Many independent solves in one set of launches (each recursion step of every
  * instance runs in one grid; the reduction partials are per tile, so every
@@ -323,6 +331,12 @@ kpm_status kpm_start_vectors(int32_t vec, int32_t complex_layout, uint64_t seed,
  *                                vectors and operators total at most this many MiB (default
  *                                192, so a wave stays in the Infinity Cache); a wave runs all
  *                                its recursion steps before the next starts.  0 = one wave
+ *   KPM_LAUNCH_TBLOCK            1 (default): solves on 2D lattices with real hopping (C <= 64
+ *                                chunks per site dividing 512, L_x >= 512/C) run two
+ *                                recursion steps per pass over the vectors (temporal
+ *                                blocking; 4 vector buffers instead of 2, bitwise the same
+ *                                vectors); 0: one step per pass.  Batched solves
+ *                                (kpm_moments_batched) always take one step per pass
  * The partial sums of the dot products are formed per work item, so the
  * moments do not depend on the grid (MAX_BLOCKS) nor on the batch an instance
  * runs in; the other keys change the work items and with them the order in
@@ -337,7 +351,8 @@ typedef enum {
     KPM_LAUNCH_ALTERNATE = 5,
     KPM_LAUNCH_SMALL = 6,
     KPM_LAUNCH_STREAMING = 7,
-    KPM_LAUNCH_WAVE_MIB = 8
+    KPM_LAUNCH_WAVE_MIB = 8,
+    KPM_LAUNCH_TBLOCK = 9
 } kpm_launch_key;
 kpm_status kpm_set_launch(int32_t key, int32_t value);
 kpm_status kpm_get_launch(int32_t key, int32_t *value);

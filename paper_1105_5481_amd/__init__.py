@@ -50,6 +50,11 @@ def lib():
         return _lib
     if not os.path.exists(_LIB_PATH):
         raise KPMError(f"libkpm.so not found at {_LIB_PATH}; build it with python paper_1105_5481_amd/build.py")
+    # PyTorch carries its own copy of the HIP runtime (same soname, different file name on its
+    # dependency list).  Loading torch first makes libkpm.so bind to that same runtime; loaded the
+    # other way round, the process would hold two HIP runtimes and the second one to initialise
+    # finds no device.
+    _torch()
     L = ctypes.CDLL(_LIB_PATH)
     P, i32, i64, u64, f64, sz = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
                                  ctypes.c_double, ctypes.c_size_t)
@@ -90,6 +95,8 @@ def lib():
         "kpm_graph_free": (None, [P]),
         "kpm_lanczos_workspace_bytes": (sz, [P, i32]),
         "kpm_green": (i32, [P, i32, i32, f64, i32, f64, f64, P, P, P, P]),
+        "kpm_last_hip_error": (ctypes.c_char_p, []),
+        "kpm_solve_mode": (i32, [P]),
         "kpm_dense_workspace_bytes": (sz, [i64, i32, i32]),
         "kpm_dense_moments": (i32, [P, i64, f64, f64, i32, i32, i32, u64, u64, P, sz, P, P]),
         "kpm_bounds_lanczos": (i32, [P, i32, u64, f64, f64, f64, P, sz, P, P]),
@@ -105,7 +112,8 @@ def lib():
 def _check(st: int, what: str):
     if st != 0:
         msg = lib().kpm_status_string(st).decode()
-        raise KPMError(f"{what}: {msg} (status {st})")
+        hip = lib().kpm_last_hip_error().decode()
+        raise KPMError(f"{what}: {msg} (status {st}; last HIP error: {hip})")
 
 
 def _torch():
@@ -554,7 +562,7 @@ def start_vectors(vec: int, complex_layout: bool, seed: int, instance: int, N: i
 LAUNCH_ELEMS_PER_THREAD, LAUNCH_MAX_BLOCKS, LAUNCH_MARCH, LAUNCH_MARCH_ITEMS, LAUNCH_XCD_SPLIT, LAUNCH_ALTERNATE, \
     LAUNCH_SMALL, LAUNCH_STREAMING = range(8)
 _LAUNCH_KEYS = {"elems_per_thread": 0, "max_blocks": 1, "march": 2, "march_items": 3, "xcd_split": 4, "alternate": 5,
-                "small": 6, "streaming": 7, "wave_mib": 8}
+                "small": 6, "streaming": 7, "wave_mib": 8, "tblock": 9}
 
 
 def set_launch(**kw):

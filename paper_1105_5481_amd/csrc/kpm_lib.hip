@@ -13,6 +13,7 @@
 #include "kpm_kernels.hpp"
 #include "kpm_lanczos.hpp"
 #include "kpm_dense.hpp"
+#include "kpm_tblock.hpp"
 
 using namespace kpm;
 
@@ -28,6 +29,7 @@ int g_alternate = 1;                    // march: odd segments walk downwards
 int g_small = 1;                        // solves whose two vector blocks fit in LDS run in one workgroup
 int g_streaming = 2;                    // march: 0 cached, 1 non-temporal access of r_{n-1}/r_{n+1}, 2 by size
 int g_wave_mib = 192;                   // batched solves: vectors + operators per wave (MiB), 0 = one wave
+int g_tblock = 1;                       // 2D real lattices: two recursion steps per pass (temporal blocking)
 constexpr uint64_t CACHE_RESIDENT_BYTES = 192ull << 20;   // below this the state stays in the 256 MiB Infinity Cache
 
 // Dynamic LDS one workgroup may use for the small-solve path (0 if no device).
@@ -49,9 +51,12 @@ size_t small_lds_limit()
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 inline hipStream_t S(void *s) { return (hipStream_t)s; }
 
+thread_local hipError_t g_last_hip = hipSuccess;   // last HIP error seen by this thread's calls
+
 kpm_status check_launch()
 {
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess) g_last_hip = e;
     return e == hipSuccess ? KPM_OK : KPM_ERR_DEVICE;
 }
 
@@ -463,6 +468,8 @@ struct kpm_solve {
     int32_t written;   // dots indices [0, written) have partials
     int32_t reduced;   // dots indices [0, reduced) are reduced
     uint64_t state;    // bytes the recursion touches per step (vectors + operator)
+    void *tbuf[4];     // temporal blocking: the four vector buffers
+    int tb_prev, tb_cur;   // ... and which of them hold r_{next-1}, r_next
 };
 
 namespace {
@@ -475,6 +482,7 @@ struct Plan {
     int32_t K, P_slots, tpt;
     size_t esz;
     size_t part_bytes, dots_bytes, buf_bytes;
+    uint32_t nbuf;    // vector buffers (2, or 4 with temporal blocking)
     uint64_t state;   // bytes the recursion touches per step (vectors + operator)
 };
 
@@ -487,7 +495,7 @@ int stream_choice(uint64_t state_bytes)
     return g_streaming == 2 ? (state_bytes > CACHE_RESIDENT_BYTES ? 1 : 0) : g_streaming;
 }
 
-bool make_plan(const kpm_ham *h, int32_t M, int32_t R, int32_t vec, Plan &p)
+bool make_plan(const kpm_ham *h, int32_t M, int32_t R, int32_t vec, Plan &p, bool allow_tb = true)
 {
     if (!h || M < 1 || R < 1 || vec < 0 || vec > 2) return false;
     std::memset(&p, 0, sizeof(p));
@@ -507,10 +515,30 @@ bool make_plan(const kpm_ham *h, int32_t M, int32_t R, int32_t vec, Plan &p)
     const uint64_t bond_bytes = (uint64_t)h->N * (h->dim ? h->dim : 1) * 2 * p.esz;
     p.wide = (nel * 16 >= (1ull << 32) || bond_bytes >= (1ull << 32)) ? 1 : 0;
     const uint64_t small_bytes = 2ull * nel * 16;
+    p.nbuf = 2;
     if (g_small && small_bytes <= small_lds_limit()) {
         p.mode = MODE_SMALL;
         p.tiles = 1;
         p.xcd = 0;
+    } else if (allow_tb && g_tblock && g_march && h->opk == OP_REAL2 && p.C <= TB_BLOCK / 8 && TB_BLOCK % p.C == 0 &&
+               h->L[0] >= TB_BLOCK / p.C && h->L[1] >= 4) {
+        // two steps per pass: x-tiles of TB_BLOCK/C - 4 owned sites, segments of rows
+        p.mode = MODE_TB;
+        p.nbuf = 4;
+        const uint32_t Tn = TB_BLOCK / p.C - 4;
+        p.P = (uint32_t)h->L[0];
+        p.Lm = (uint32_t)h->L[1];
+        p.nct = (p.P + Tn - 1) / Tn;
+        // a block marches with two barriers per row, so more and shorter segments than
+        // the one-step kernels (8x the item target; measured on the 2048^2 lattice:
+        // 4096 items 455 us per step, 512 items 554 us)
+        const uint64_t target = 8ull * (uint64_t)g_march_items;
+        uint32_t nseg = (uint32_t)((target + p.nct - 1) / p.nct);
+        nseg = std::max<uint32_t>(1, std::min<uint32_t>(nseg, std::max<uint32_t>(1, p.Lm / 8)));
+        p.S = (p.Lm + nseg - 1) / nseg;
+        p.nseg = (p.Lm + p.S - 1) / p.S;
+        p.tiles = p.nct * p.nseg;
+        p.xcd = p.nct >= 8 ? 1 : 0;
     } else if (h->dim && g_march) {
         p.mode = MODE_MARCH;
         p.P = (uint32_t)(h->dim == 3 ? h->L[0] * h->L[1] : h->L[0]);
@@ -554,7 +582,7 @@ bool make_plan(const kpm_ham *h, int32_t M, int32_t R, int32_t vec, Plan &p)
     return true;
 }
 
-size_t instance_bytes(const Plan &p) { return p.part_bytes + p.dots_bytes + 2 * p.buf_bytes; }
+size_t instance_bytes(const Plan &p) { return p.part_bytes + p.dots_bytes + p.nbuf * p.buf_bytes; }
 
 void fill_inst(const kpm_ham *h, const Plan &p, int32_t M, int32_t R, int32_t vec, uint64_t seed, uint64_t instance,
                char *region, Inst &I)
@@ -607,6 +635,20 @@ void fill_inst(const kpm_ham *h, const Plan &p, int32_t M, int32_t R, int32_t ve
     I.buf0 = region + p.part_bytes + p.dots_bytes;
     I.buf1 = region + p.part_bytes + p.dots_bytes + p.buf_bytes;
     I.mu = nullptr;
+}
+
+kpm_status launch_tb(int prec, int wide, int nt, const Inst *tab, uint32_t blocks, int32_t n, int32_t phase,
+                     const void *prev, void *cur, void *out1, void *out2, hipStream_t st)
+{
+    typedef void (*tb_fn)(const Inst *, int32_t, int32_t, const void *, void *, void *, void *);
+    static const tb_fn fns[2][2][2] = {
+        {{k_step_tb<double, false, false>, k_step_tb<double, false, true>},
+         {k_step_tb<double, true, false>, k_step_tb<double, true, true>}},
+        {{k_step_tb<float, false, false>, k_step_tb<float, false, true>},
+         {k_step_tb<float, true, false>, k_step_tb<float, true, true>}}};
+    const tb_fn f = fns[prec == KPM_F64 ? 0 : 1][wide ? 1 : 0][nt ? 1 : 0];
+    hipLaunchKernelGGL(f, dim3(blocks), dim3(TB_BLOCK), 0, st, tab, n, phase, prev, cur, out1, out2);
+    return check_launch();
 }
 
 kpm_status launch_init(int prec, int wide, const Inst *tab, const uint32_t *bmap, uint32_t blocks, hipStream_t st)
@@ -703,6 +745,8 @@ bool valid_desc(const kpm_ham_desc *d)
 }  // namespace
 
 extern "C" {
+
+const char *kpm_last_hip_error(void) { return hipGetErrorString(g_last_hip); }
 
 const char *kpm_status_string(kpm_status st)
 {
@@ -839,7 +883,8 @@ kpm_status kpm_build(const kpm_ham_desc *d, double a, double b, int32_t prec, vo
     if (!h) return KPM_ERR_OUT_OF_MEMORY;
     HamLayout L;
     ham_layout(d, prec, *h, L);
-    if (hipMalloc((void **)&h->mem, L.bytes) != hipSuccess) {
+    if (hipError_t me = hipMalloc((void **)&h->mem, L.bytes); me != hipSuccess) {
+        g_last_hip = me;
         delete h;
         return KPM_ERR_OUT_OF_MEMORY;
     }
@@ -940,6 +985,24 @@ kpm_status kpm_solve_begin(kpm_ham *h, int32_t M, int32_t R, int32_t vec, uint64
         *out = s;
         return KPM_OK;
     }
+    if (p.mode == MODE_TB) {
+        // four vector buffers; r_0 goes to buffer 1 (buffer 0 plays r_{-1}, never read)
+        char *b = s->ws + align256(sizeof(Inst)) + p.part_bytes + p.dots_bytes;
+        for (int q = 0; q < 4; ++q) s->tbuf[q] = b + (size_t)q * p.buf_bytes;
+        s->tb_prev = 0;
+        s->tb_cur = 1;
+        if (e == KPM_OK) e = launch_tb(h->prec, p.wide, p.nt, s->tab_dev, p.nb, 0, 0, s->tbuf[0], s->tbuf[1],
+                                       s->tbuf[2], s->tbuf[3], st);
+        s->written = 1;
+        s->reduced = 0;
+        s->next = 0;
+        if (e != KPM_OK) {
+            delete s;
+            return e;
+        }
+        *out = s;
+        return KPM_OK;
+    }
     if (e == KPM_OK) e = launch_init(h->prec, p.wide, s->tab_dev, nullptr, p.nb, st);
     s->written = 1;
     s->reduced = 0;
@@ -973,6 +1036,34 @@ kpm_status kpm_solve_advance(kpm_solve *s, int32_t max_steps, void *stream, int3
     hipStream_t st = S(stream);
     const Inst &I = s->inst;
     kpm_status e = KPM_OK;
+    if (I.mode == MODE_TB) {
+        // pairs of steps; a single step for an odd remainder or a budget of one
+        int32_t done = 0;
+        while (done < max_steps && s->next < I.K && e == KPM_OK) {
+            const bool two = (I.K - s->next >= 2) && (max_steps - done >= 2);
+            const int32_t adv = two ? 2 : 1;
+            if (s->written - s->reduced + adv > I.pslots) e = solve_reduce_pending(s, st);
+            if (e != KPM_OK) break;
+            int f[2], nf = 0;
+            for (int q = 0; q < 4; ++q)
+                if (q != s->tb_prev && q != s->tb_cur) f[nf++] = q;
+            e = launch_tb(s->h->prec, s->wide, I.nt, s->tab_dev, I.nb, s->next, two ? 1 : 2, s->tbuf[s->tb_prev],
+                          s->tbuf[s->tb_cur], s->tbuf[f[0]], s->tbuf[f[1]], st);
+            if (two) {
+                s->tb_prev = f[0];
+                s->tb_cur = f[1];
+            } else {
+                s->tb_prev = s->tb_cur;
+                s->tb_cur = f[0];
+            }
+            s->next += adv;
+            s->written += adv;
+            done += adv;
+        }
+        if (e == KPM_OK && s->written - s->reduced >= I.pslots) e = solve_reduce_pending(s, st);
+        if (remaining) *remaining = I.K - s->next;
+        return e;
+    }
     for (int32_t c = 0; c < max_steps && s->next < I.K && e == KPM_OK; ++c) {
         if (s->written - s->reduced >= I.pslots) e = solve_reduce_pending(s, st);
         if (e != KPM_OK) break;
@@ -1000,6 +1091,8 @@ kpm_status kpm_solve_finish(kpm_solve *s, double *mu_dev, void *stream)
 }
 
 void kpm_solve_free(kpm_solve *s) { delete s; }
+
+int32_t kpm_solve_mode(const kpm_solve *s) { return s ? s->inst.mode : -1; }
 
 kpm_status kpm_moments(kpm_ham *h, int32_t M, int32_t R, int32_t vec, uint64_t seed, uint64_t instance, void *ws,
                        size_t ws_bytes, double *mu_dev, void *stream)
@@ -1169,7 +1262,7 @@ bool batch_layout(kpm_ham *const *h, int32_t count, const int32_t *M, const int3
     std::vector<int> small, rest;
     for (int i = 0; i < count; ++i) {
         if (!h[i] || h[i]->prec != L.prec) return false;
-        if (!make_plan(h[i], M[i], R[i], vec, L.plans[i])) return false;
+        if (!make_plan(h[i], M[i], R[i], vec, L.plans[i], false)) return false;
         if (L.plans[i].mode == MODE_SMALL) {
             small.push_back(i);
         } else {
@@ -1375,8 +1468,15 @@ kpm_status kpm_batch_advance(kpm_batch *b, int32_t steps, void *stream)
     // active members grouped by kernel class; the table also carries each
     // member's pending reduction range
     std::vector<kpm_solve *> act;
-    for (kpm_solve *s : b->members)
+    for (kpm_solve *s : b->members) {
+        if (s->inst.mode == MODE_TB) {   // temporally blocked solves advance with their own launches
+            if (s->next < s->inst.K) {
+                if (kpm_status r = kpm_solve_advance(s, steps, stream, nullptr)) return r;
+            }
+            continue;
+        }
         if (s->inst.mode != MODE_SMALL && (s->next < s->inst.K || s->written > s->reduced)) act.push_back(s);
+    }
     if (act.empty() || steps == 0) return KPM_OK;
     // the members of one launch share the caches
     uint64_t state = 0;
@@ -1457,7 +1557,7 @@ kpm_status kpm_graph_capture_batched(kpm_ham *const *h, int32_t count, const int
     // set LDS limits of the small-solve kernels outside the capture
     for (int i = 0; i < count; ++i) {
         Plan p;
-        if (h && h[i] && M && R && make_plan(h[i], M[i], R[i], vec, p) && p.mode == MODE_SMALL) {
+        if (h && h[i] && M && R && make_plan(h[i], M[i], R[i], vec, p, false) && p.mode == MODE_SMALL) {
             small_fn f = h[i]->prec == KPM_F64 ? small_for<double>(h[i]->opk) : small_for<float>(h[i]->opk);
             if (hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)small_lds_limit()) != hipSuccess)
@@ -1528,7 +1628,7 @@ bool lanczos_plan(const kpm_ham *h, int32_t k, Plan &p, int32_t &vec)
 {
     if (!h || h->prec != KPM_F64 || k < 1 || k > LZ_KMAX) return false;
     vec = h->cplx_op ? KPM_VEC_PHASE : KPM_VEC_RADEMACHER;
-    if (!make_plan(h, 2, 1, vec, p)) return false;
+    if (!make_plan(h, 2, 1, vec, p, false)) return false;
     p.mode = MODE_FLAT;
     const uint64_t per_tile = (uint64_t)BLOCK * p.tpt;
     p.tiles = (uint32_t)((p.nel + per_tile - 1) / per_tile);
@@ -1797,6 +1897,10 @@ kpm_status kpm_set_launch(int32_t key, int32_t value)
         if (value < 0 || value > (1 << 22)) return KPM_ERR_INVALID_ARG;
         g_wave_mib = value;
         return KPM_OK;
+    case KPM_LAUNCH_TBLOCK:
+        if (value != 0 && value != 1) return KPM_ERR_INVALID_ARG;
+        g_tblock = value;
+        return KPM_OK;
     }
     return KPM_ERR_INVALID_ARG;
 }
@@ -1814,6 +1918,7 @@ kpm_status kpm_get_launch(int32_t key, int32_t *value)
     case KPM_LAUNCH_SMALL: *value = g_small; return KPM_OK;
     case KPM_LAUNCH_STREAMING: *value = g_streaming; return KPM_OK;
     case KPM_LAUNCH_WAVE_MIB: *value = g_wave_mib; return KPM_OK;
+    case KPM_LAUNCH_TBLOCK: *value = g_tblock; return KPM_OK;
     }
     return KPM_ERR_INVALID_ARG;
 }

@@ -77,7 +77,7 @@ def test_argument_validation_without_device(L):
     assert L.kpm_set_launch(3, 0) == 1
     assert L.kpm_set_launch(4, 4) == 1
     assert L.kpm_set_launch(5, 2) == 1
-    assert L.kpm_set_launch(9, 1) == 1
+    assert L.kpm_set_launch(99, 1) == 1
     d = kpm.HamDesc()
     d.kind = 3
     d.L[0], d.L[1], d.L[2] = 4, 0, 4             # zero extent
@@ -100,9 +100,10 @@ def test_lanczos_argument_validation(L):
 def test_launch_settings_roundtrip(L):
     old = kpm.get_launch()
     with kpm.launch_settings(elems_per_thread=2, max_blocks=1024, march=0, march_items=64, xcd_split=3, alternate=0,
-                             small=0, streaming=0, wave_mib=0):
+                             small=0, streaming=0, wave_mib=0, tblock=0):
         assert kpm.get_launch() == {"elems_per_thread": 2, "max_blocks": 1024, "march": 0, "march_items": 64,
-                                    "xcd_split": 3, "alternate": 0, "small": 0, "streaming": 0, "wave_mib": 0}
+                                    "xcd_split": 3, "alternate": 0, "small": 0, "streaming": 0, "wave_mib": 0,
+                                    "tblock": 0}
     assert kpm.get_launch() == old
 
 
