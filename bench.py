@@ -43,6 +43,54 @@ CONFIG3_KERNEL = "k_step_march<float, OP_SPIN3> (multi-instance)"
 FP64_MFMA_PEAK_TFLOPS = 78.6
 
 
+def bench_aux(args, log_fn):
+    """The steps around the path on the 64^3 spin lattice: the Lanczos interval (FP64, k = 100
+    steps) against Gershgorin, and local DoS / site Green's functions at 64 sites (unit start
+    vectors, one R = 1 solve per site in one batched call, M = 1024, Lorentz kernel, K = 2048)."""
+    import numpy as np
+    import torch
+    import paper_1105_5481_amd as kpm
+    from paper_1105_5481_amd import workloads as wl
+    lat = wl.config2()["lattice"]
+    N = lat.N
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record()
+        for _ in range(reps):
+            r = fn()
+        e1.record()
+        e1.synchronize()
+        return r, (time.perf_counter() - t0) / reps, e0.elapsed_time(e1) * 1e-3 / reps
+
+    g_lo, g_hi = kpm.gershgorin(lat)
+    h64 = kpm.Hamiltonian(lat, 1.0, 0.0, kpm.F64)
+    lz, lz_wall, lz_gpu = timed(lambda: kpm.lanczos_bounds(h64, 100, 0, 0.005, (g_lo, g_hi)), max(1, args.steps))
+    h64.free()
+    a, b = kpm.scale_from_bounds(lz["e_lo"], lz["e_hi"], 0.01)
+    log_fn(f"bench: aux: Lanczos k=100 {lz_wall * 1e3:.2f} ms, interval [{lz['e_lo']:.5f}, {lz['e_hi']:.5f}] "
+           f"vs Gershgorin [{g_lo:.4f}, {g_hi:.4f}]")
+    h32 = kpm.Hamiltonian(lat, a, b, kpm.F32)
+    sites = [int(x) for x in np.random.default_rng(1007).choice(N, 64, replace=False)]
+    M, K = 1024, 2048
+    (om, G), g_wall, g_gpu = timed(lambda: kpm.site_green(h32, sites, M, K, kpm.KERNEL_LORENTZ, 4.0), max(1, args.steps))
+    mu = kpm.site_moments(h32, sites[:1], M)[0]
+    _, gr_wall, gr_gpu = timed(lambda: kpm.green(mu, K, a, b, kpm.KERNEL_LORENTZ, 4.0), 10)
+    h32.free()
+    log_fn(f"bench: aux: site Green's functions at 64 sites {g_wall * 1e3:.2f} ms; one kpm_green {gr_gpu * 1e6:.1f} us")
+    return {"metric": "aux: Lanczos interval and site Green's functions", "unit": "ms", "n_gpus": 1, "data": "synthetic",
+            "config": {"workload": WORKLOAD_TEXT["config2"] + " (operator only)", "N": N},
+            "lanczos": {"k": 100, "ms": lz_wall * 1e3, "gpu_ms": lz_gpu * 1e3, "e_lo": lz["e_lo"], "e_hi": lz["e_hi"],
+                        "gershgorin": [g_lo, g_hi], "width_ratio": (lz["e_hi"] - lz["e_lo"]) / (g_hi - g_lo),
+                        "steps_used": lz["m"]},
+            "site_green": {"sites": len(sites), "M": M, "K": K, "precision": "c64 recursion, FP64 moments",
+                           "ms": g_wall * 1e3, "gpu_ms": g_gpu * 1e3, "updates_per_s": len(sites) * N * M / g_wall,
+                           "kpm_green_us": gr_gpu * 1e6}}
+
+
 def bench_dense(args, log_fn):
     """The dense-H recursion on the matrix cores at the shapes of the paper's dense experiments
     (R x S = 1792 vectors): E1 (the 10^3 lattice as a dense matrix, M=1024), E3 (D=128, M=2048),
@@ -350,12 +398,21 @@ def cpu_baseline(lat, a, b, vec, seed):
     oracle.build()
     threads = oracle.max_threads()
     Ms, Rs = (1024, 32) if lat.N <= 300000 else (64, 8)
-    t0 = time.perf_counter()
-    oracle.moments_lattice(lat.dim, lat.L[:lat.dim], lat.t, a, b, Ms, Rs, vec_kind=vec, seed=seed,
-                           hop=lat.hop, onsite=lat.onsite, spinor=lat.spinor)
-    dt = time.perf_counter() - t0
+
+    def run(M_, R_, nthreads):
+        t0 = time.perf_counter()
+        oracle.moments_lattice(lat.dim, lat.L[:lat.dim], lat.t, a, b, M_, R_, vec_kind=vec, seed=seed,
+                               hop=lat.hop, onsite=lat.onsite, spinor=lat.spinor, nthreads=nthreads)
+        return time.perf_counter() - t0
+
+    dt = run(Ms, Rs, threads)
+    # one thread, on a smaller sample, median of 3 runs
+    M1, R1 = (64, 4) if lat.N <= 300000 else (16, 4)
+    d1 = sorted(run(M1, R1, 1) for _ in range(3))[1]
     return {"value": lat.N * Ms * Rs / dt, "unit": UNIT, "cores": threads, "kind": "oracle",
-            "sample": f"full {lat.N}-site lattice, M={Ms} moments, R={Rs} vectors ({dt:.1f} s)"}
+            "sample": f"full {lat.N}-site lattice, M={Ms} moments, R={Rs} vectors ({dt:.1f} s)",
+            "single_thread": {"value": lat.N * M1 * R1 / d1, "cores": 1,
+                              "sample": f"M={M1}, R={R1}, median of 3 runs ({d1:.2f} s each)"}}
 
 
 def main():
@@ -387,7 +444,8 @@ def main():
     ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/traffic.json for --workload from the FETCH_SIZE and WRITE_SIZE runs "
                          "of one profiled solve (--steps 1 --warmup 0 --calib-copy) and exit")
-    ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config4", "config5", "dense"],
+    ap.add_argument("--workload", default="config2",
+                    choices=["config2", "config3", "config4", "config5", "dense", "aux"],
                     help="config2 (the measured workload), config3 (256-cube batch), config4 (2D 2048^2, R=64, real FP32), config5 (serving record)")
     args = ap.parse_args()
 
@@ -452,6 +510,9 @@ def main():
         return
     if args.workload == "dense":
         print(json.dumps(bench_dense(args, log)), flush=True)
+        return
+    if args.workload == "aux":
+        print(json.dumps(bench_aux(args, log)), flush=True)
         return
     cfg = wl.config2() if args.workload == "config2" else wl.config4()
     lat, M, R, vec, seed = cfg["lattice"], cfg["M"], cfg["R"], cfg["vec"], cfg["seed"]
