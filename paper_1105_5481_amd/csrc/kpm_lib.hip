@@ -309,50 +309,67 @@ __device__ inline double kernel_coef(int kind, int n, int M, double lam, double 
     return 1.0;
 }
 
-// Sums over n of w_n cos(n theta_k) (and w_n sin(n theta_k) when fs is
-// wanted), w_n = (2 - delta_n0) g_n mu_n, for the thread's Chebyshev point
-// theta_k = pi (k + 1/2)/K; n theta_k is reduced exactly as pi m/(2K) with
-// m = n (2k+1) mod 4K.  Every thread of the block takes part (LDS staging).
-__device__ inline void chebyshev_sums(const double *mu, int M, int kind, double lam, int K, int k, double &fc,
-                                      double *fs)
+// Sums over n of w_n cos(n theta_k) (and w_n sin(n theta_k) when `sine`),
+// w_n = (2 - delta_n0) g_n mu_n, at the Chebyshev points theta_k = pi (k + 1/2)/K.
+// A block of 256 threads takes DOS_PTS points: thread t works on point
+// k = k0 + t % DOS_PTS and on the terms n = t / DOS_PTS (mod DOS_RES); the
+// DOS_RES partial sums of a point are then added in a fixed order.  n theta_k
+// is reduced exactly as pi m/(2K) with m = n (2k+1) mod 4K.  The w_n are
+// staged through LDS in chunks.  Returns the sums for the calling thread's
+// point in (fc, fs) on threads t < DOS_PTS (the others return zeros).
+constexpr int DOS_PTS = 16;
+constexpr int DOS_RES = 256 / DOS_PTS;
+__device__ inline void chebyshev_sums(const double *mu, int M, int kind, double lam, int K, bool sine, double &fc,
+                                      double &fs)
 {
     __shared__ double w[DOS_CHUNK];
-    const uint64_t step = 2 * (uint64_t)k + 1, fourK = 4 * (uint64_t)K;
+    __shared__ double red[2][DOS_RES][DOS_PTS];
+    const int t = threadIdx.x, p = t % DOS_PTS, q = t / DOS_PTS;
+    const int k = blockIdx.x * DOS_PTS + p;
+    const uint64_t fourK = 4 * (uint64_t)K;
+    const uint64_t step = (uint64_t)DOS_RES * (2 * (uint64_t)k + 1) % fourK;   // m advance per DOS_RES terms
     const double inv2K = 1.0 / (2.0 * (double)K);
     const double cot1 = cospi(1.0 / (double)(M + 1)) / sinpi(1.0 / (double)(M + 1));
-    uint64_t m = 0;                                   // n (2k+1) mod 4K for the current n
-    fc = 0.0;
-    double s = 0.0;
+    uint64_t m = (uint64_t)q * (2 * (uint64_t)k + 1) % fourK;                // m for n = q
+    double c = 0.0, s = 0.0;
     for (int n0 = 0; n0 < M; n0 += DOS_CHUNK) {
         const int nn = min(DOS_CHUNK, M - n0);
         __syncthreads();
-        for (int u = threadIdx.x; u < nn; u += blockDim.x) {
+        for (int u = t; u < nn; u += blockDim.x) {
             const int n = n0 + u;
             w[u] = (n == 0 ? 1.0 : 2.0) * kernel_coef(kind, n, M, lam, cot1) * mu[n];
         }
         __syncthreads();
         if (k < K) {
-            for (int u = 0; u < nn; ++u) {
-                const double t = (double)m * inv2K;
-                fc += w[u] * cospi(t);
-                if (fs) s += w[u] * sinpi(t);
+            for (int u = q; u < nn; u += DOS_RES) {
+                const double a = (double)m * inv2K;
+                c += w[u] * cospi(a);
+                if (sine) s += w[u] * sinpi(a);
                 m += step;
                 if (m >= fourK) m -= fourK;
-                if (m >= fourK) m %= fourK;
             }
         }
     }
-    if (fs) *fs = s;
+    red[0][q][p] = c;
+    red[1][q][p] = s;
+    __syncthreads();
+    fc = 0.0;
+    fs = 0.0;
+    if (t < DOS_PTS)
+        for (int r = 0; r < DOS_RES; ++r) {
+            fc += red[0][r][t];
+            fs += red[1][r][t];
+        }
 }
 
-// density of states, Eq. (fKPM), one thread per Chebyshev point
+// density of states, Eq. (fKPM)
 __global__ __launch_bounds__(256) void k_dos(const double *mu, int M, int jackson, int K, double a, double b,
                                              double *omega, double *rho)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    double f;
-    chebyshev_sums(mu, M, jackson ? 1 : 0, 0.0, K, k, f, nullptr);
-    if (k < K) {
+    double f, unused;
+    chebyshev_sums(mu, M, jackson ? 1 : 0, 0.0, K, false, f, unused);
+    const int k = blockIdx.x * DOS_PTS + threadIdx.x;
+    if (threadIdx.x < DOS_PTS && k < K) {
         const double th = ((double)k + 0.5) / (double)K;
         omega[k] = a * cospi(th) + b;
         rho[k] = f / (M_PI * sinpi(th)) / a;
@@ -365,10 +382,10 @@ __global__ __launch_bounds__(256) void k_dos(const double *mu, int M, int jackso
 __global__ __launch_bounds__(256) void k_green(const double *mu, int M, int kind, double lam, int K, double a,
                                                double b, double *omega, double *gre, double *gim)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
     double fc, fs;
-    chebyshev_sums(mu, M, kind, lam, K, k, fc, &fs);
-    if (k < K) {
+    chebyshev_sums(mu, M, kind, lam, K, true, fc, fs);
+    const int k = blockIdx.x * DOS_PTS + threadIdx.x;
+    if (threadIdx.x < DOS_PTS && k < K) {
         const double th = ((double)k + 0.5) / (double)K;
         const double sn = sinpi(th);
         omega[k] = a * cospi(th) + b;
@@ -1829,7 +1846,7 @@ kpm_status kpm_dos(const double *mu_dev, int32_t M, int32_t jackson, int32_t K, 
                    double *rho_dev, void *stream)
 {
     if (!mu_dev || !omega_dev || !rho_dev || M < 1 || K < 1 || !(a > 0.0) || !std::isfinite(b)) return KPM_ERR_INVALID_ARG;
-    hipLaunchKernelGGL(k_dos, dim3((K + 255) / 256), dim3(256), 0, S(stream), mu_dev, M, jackson ? 1 : 0, K, a, b,
+    hipLaunchKernelGGL(k_dos, dim3((K + DOS_PTS - 1) / DOS_PTS), dim3(256), 0, S(stream), mu_dev, M, jackson ? 1 : 0, K, a, b,
                        omega_dev, rho_dev);
     return check_launch();
 }
@@ -1840,7 +1857,7 @@ kpm_status kpm_green(const double *mu_dev, int32_t M, int32_t kernel, double lam
     if (!mu_dev || !omega_dev || !g_re_dev || !g_im_dev || M < 1 || K < 1 || kernel < 0 || kernel > 2 ||
         !(a > 0.0) || !std::isfinite(b) || (kernel == 2 && !(lambda > 0.0 && lambda < 700.0)))
         return KPM_ERR_INVALID_ARG;
-    hipLaunchKernelGGL(k_green, dim3((K + 255) / 256), dim3(256), 0, S(stream), mu_dev, M, kernel, lambda, K, a, b,
+    hipLaunchKernelGGL(k_green, dim3((K + DOS_PTS - 1) / DOS_PTS), dim3(256), 0, S(stream), mu_dev, M, kernel, lambda, K, a, b,
                        omega_dev, g_re_dev, g_im_dev);
     return check_launch();
 }
