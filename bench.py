@@ -254,7 +254,7 @@ def kernel_source_digest():
 
 
 TRAFFIC_PATH = os.path.join(ROOT, "profiles", "traffic.json")
-FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0     # calibrated on a plain device copy (measurement)
+FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0     # a plain 1 GiB device copy reads 1/2 of its bytes by FETCH_SIZE, writes 1/1
 
 
 def measured_traffic(workload, kernel):
@@ -470,7 +470,7 @@ def main():
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
-        log("bench.py: only --gpus 1 is supported (single-GPU build; sharding is described in DESIGN.md)")
+        log("bench.py: only --gpus 1 is supported (one process on one GPU)")
         sys.exit(2)
 
     import torch

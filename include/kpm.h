@@ -240,8 +240,8 @@ size_t kpm_request_bytes(const kpm_ham_desc *desc, int32_t prec, int32_t M, int3
 /* Device bytes the operator of a built handle occupies. */
 size_t kpm_ham_bytes(const kpm_ham *h);
 
-/* Dynamic batches (continuous batching, the serving pattern of the north-star's
- * point (3)): a set of begun solves (kpm_solve_begin) that advance together.
+/* Dynamic batches (continuous batching, for serving streams of requests): a set
+ * of begun solves (kpm_solve_begin) that advance together.
  * kpm_batch_advance enqueues up to `steps` (<= 64) recursion steps in which
  * every launch covers all member solves of one operator class, each at its own
  * step n, so solves that joined at different times share launches; members

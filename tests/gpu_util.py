@@ -5,7 +5,7 @@ import oracle
 import paper_1105_5481_amd as kpm
 from paper_1105_5481_amd import workloads as wl
 
-# FP64 parity (the spec bar): |mu_gpu - mu_oracle| <= REL64 * max(|mu_oracle|, FLOOR64).
+# FP64 parity bar: |mu_gpu - mu_oracle| <= REL64 * max(|mu_oracle|, FLOOR64).
 # Both sides evaluate the same vectors with the same per-element operation order and
 # double-double dots; the floor only guards moments that are zero up to rounding.
 REL64 = 1e-12
