@@ -12,11 +12,14 @@ from tests import gpu_util as gu
 
 pytestmark = pytest.mark.gpu
 
-CASES = [  # (Lx, Ly, W, R, prec, M): C = 4, 1, 16, 16 chunks per site -> windows of 256, 1024, 64, 64 sites
+CASES = [  # (Lx, Ly, W, R, prec, M): C = 4, 1, 16, 16 chunks per site -> windows of 128, 512, 32, 32 sites
     (300, 40, 1.0, 8, kpm.F64, 64),
     (1024, 9, 0.0, 2, kpm.F64, 33),
     (130, 70, 2.0, 64, kpm.F32, 101),
     (64, 64, 1.0, 64, kpm.F32, 40),
+    (200, 30, 1.0, 8, kpm.F64, 1),     # start vectors only
+    (200, 30, 1.0, 8, kpm.F64, 2),     # one single step
+    (200, 30, 1.0, 8, kpm.F64, 5),     # a pair and a single step
 ]
 
 
