@@ -330,12 +330,14 @@ def pmc_summary(root):
         print(f"{name} grid={grid}: {vals}")
 
 
-def serving_leg(n_requests, logN_max, load, seed=1005):
+def serving_leg(n_requests, logN_max, load, seed=1005, fp64_stable=0.0):
     """Config-5 recipe (Poisson arrivals; N log-uniform from 2^12 up to 2^logN_max; 2D/3D; real or
     spin hopping; M in {256, 1024, 4096, 8192}; R in [8, 64]).  Capacity of the batched FP32 server
     is measured with every request present at t = 0; a wall-clock trace at each offered load
     (`load`: one value or a list) x capacity is then served by it and replayed through the plain
-    FP64 first-come-first-served path (one solve at a time)."""
+    FP64 first-come-first-served path (one solve at a time).  With fp64_stable > 0, both are also
+    run at fp64_stable x the FP64 capacity (the isolated FP64 service rate), a rate the plain path
+    can sustain."""
     loads = [load] if isinstance(load, (int, float)) else list(load)
     import numpy as np
     import paper_1105_5481_amd as kpm
@@ -387,6 +389,20 @@ def serving_leg(n_requests, logN_max, load, seed=1005):
                                          "p99": float(np.percentile(svc64, 99) * 1e3),
                                          "mean": float(svc64.mean() * 1e3)},
             "fp64_capacity_req_per_s": cap64, "fp64_stable_at_this_rate": bool(ld * capacity < cap64)})
+    if fp64_stable > 0 and out["loads"]:
+        rate = fp64_stable * out["loads"][-1]["fp64_capacity_req_per_s"]
+        arrivals = np.cumsum(gaps / rate)
+        log(f"bench: FP64-stable rate {rate:.2f} req/s: trace over {arrivals[-1]:.2f} s")
+        srv = Server(prec=kpm.F32, max_active=64, chunk=32)
+        served = srv.run(reqs(arrivals), clock="wall", progress=log)
+        srv.close()
+        srv = Server(prec=kpm.F64, max_active=1, chunk=64)
+        plain = srv.run(reqs(arrivals), clock="wall", progress=log)
+        srv.close()
+        log(f"bench: FP64-stable rate: FP32 {latency_stats(served)}, FP64 {latency_stats(plain)}")
+        out["at_fp64_stable_rate"] = {"fraction_of_fp64_capacity": fp64_stable, "arrival_rate_req_per_s": rate,
+                                      "offered_load_fp32": rate / capacity, "fp32_served": latency_stats(served),
+                                      "fp64_fcfs": latency_stats(plain)}
     if len(loads) == 1:      # flat layout for the single-load leg of the default run
         out.update(out.pop("loads")[0])
     return out
@@ -426,6 +442,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=160)
     ap.add_argument("--serve-logn-max", type=float, default=18.0)
+    ap.add_argument("--serve-fp64-stable", type=float, default=0.0,
+                    help="config5: also serve at this fraction of the FP64 capacity (0: off)")
     ap.add_argument("--serve-load", type=lambda v: [float(x) for x in v.split(",")], default=[0.7],
                     help="offered load(s) as a fraction of the measured FP32 capacity, comma separated")
     ap.add_argument("--tpt", type=int, default=0, help="chunks per thread per tile (1, 2, 4)")
@@ -500,7 +518,7 @@ def main():
 
     if args.workload == "config5":
         # the serving record alone: FP32 continuous batching vs the plain FP64 FCFS path
-        sv = serving_leg(args.serve_requests, args.serve_logn_max, args.serve_load)
+        sv = serving_leg(args.serve_requests, args.serve_logn_max, args.serve_load, fp64_stable=args.serve_fp64_stable)
         print(json.dumps({"metric": "p50/p99 solve latency under a Poisson request stream", "unit": "ms",
                           "n_gpus": 1, "data": "synthetic", "higher_is_better": False,
                           "config": {"workload": WORKLOAD_TEXT["config5"]}, "serving": sv}), flush=True)
