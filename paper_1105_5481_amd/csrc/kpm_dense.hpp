@@ -46,13 +46,13 @@ __global__ __launch_bounds__(256) void k_dense_scale(const double *__restrict__ 
 // V_0 = xi (R real start vectors of kind vec, column r = vector r) over the
 // output tiles of the step kernel, with the partials of <V_0|V_0> (slot 0).
 __global__ __launch_bounds__(256) void k_dense_init(uint32_t D, uint32_t Dp, uint32_t R, uint32_t Rp, int vec,
-                                                    uint64_t seed, uint64_t instance, double *__restrict__ V,
-                                                    double *__restrict__ part)
+                                                    uint64_t seed, uint64_t instance, uint32_t tm,
+                                                    double *__restrict__ V, double *__restrict__ part)
 {
     const uint32_t tiles_r = Rp / DN_TILE;
-    const uint32_t i0 = (blockIdx.x / tiles_r) * DN_TILE, r0 = (blockIdx.x % tiles_r) * DN_TILE;
+    const uint32_t i0 = (blockIdx.x / tiles_r) * tm, r0 = (blockIdx.x % tiles_r) * DN_TILE;
     double s = 0.0, c = 0.0;
-    for (uint32_t q = threadIdx.x; q < DN_TILE * DN_TILE; q += 256) {
+    for (uint32_t q = threadIdx.x; q < tm * DN_TILE; q += 256) {
         const uint32_t i = i0 + q / DN_TILE, r = r0 + q % DN_TILE;
         double re = 0.0, im = 0.0;
         if (i < D && r < R) {
@@ -68,68 +68,87 @@ __global__ __launch_bounds__(256) void k_dense_init(uint32_t D, uint32_t Dp, uin
 
 // One recursion step: next = H~ cur (FIRST) or 2 H~ cur - next, and the
 // partials of <next|next>, <next|cur> for the dots index of this step.
-template <bool FIRST>
+// The block computes TM x 64 outputs (TM = 64: waves in 2 x 2 quarters of
+// 32 x 32; TM = 128: waves in 4 row bands of 32 x 64, so every A value feeds 4
+// matrix instructions).
+template <bool FIRST, int TM>
 __global__ __launch_bounds__(256) void k_dense_step(const double *__restrict__ Ht, const double *__restrict__ cur,
                                                     double *__restrict__ next, uint32_t Dp, uint32_t Rp,
                                                     double *__restrict__ part)
 {
-    __shared__ double As[DN_TILE][DN_KT + 1];
+    constexpr int WR = TM == 128 ? 32 : 32;          // rows per wave
+    constexpr int WC = TM == 128 ? 64 : 32;          // columns per wave
+    constexpr int NP = WR / 16, NQ = WC / 16;        // instruction tiles per wave
+    constexpr int AL = TM * DN_KT / 256;             // A values staged per thread per slice
+    __shared__ double As[TM][DN_KT + 1];
     __shared__ double Bs[DN_KT][DN_TILE + 2];
     const uint32_t tiles_r = Rp / DN_TILE;
-    const uint32_t i0 = (blockIdx.x / tiles_r) * DN_TILE, r0 = (blockIdx.x % tiles_r) * DN_TILE;
+    const uint32_t i0 = (blockIdx.x / tiles_r) * TM, r0 = (blockIdx.x % tiles_r) * DN_TILE;
     const int t = threadIdx.x, l = t & 63, w = t >> 6;
-    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;     // this wave's 32 x 32 quarter
+    const int wr = TM == 128 ? 32 * w : (w >> 1) * 32, wc = TM == 128 ? 0 : (w & 1) * 32;
     const int lr = l & 15, lk = l >> 4;
-    dn_d4 acc[2][2];
+    dn_d4 acc[NP][NQ];
 #pragma unroll
-    for (int p = 0; p < 2; ++p)
+    for (int p = 0; p < NP; ++p)
 #pragma unroll
-        for (int q = 0; q < 2; ++q) acc[p][q] = dn_d4{0.0, 0.0, 0.0, 0.0};
-    // the slices H~[i0:i0+64, k0:k0+16] and cur[k0:k0+16, r0:r0+64] (1024 values
-    // each, 4 per thread); the next slice is loaded into registers while the
-    // matrix instructions work on the current one in LDS
-    double ra[4], rb[4];
+        for (int q = 0; q < NQ; ++q) acc[p][q] = dn_d4{0.0, 0.0, 0.0, 0.0};
+    // the slices H~[i0:i0+TM, k0:k0+16] and cur[k0:k0+16, r0:r0+64]; the next
+    // slice is loaded into registers while the matrix instructions work on the
+    // current one in LDS
+    double ra[AL], rb[4];
+#pragma unroll
+    for (int u = 0; u < AL; ++u) {
+        const int q = t + 256 * u;
+        ra[u] = Ht[(uint64_t)(i0 + (q >> 4)) * Dp + (q & 15)];
+    }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         const int q = t + 256 * u;
-        ra[u] = Ht[(uint64_t)(i0 + (q >> 4)) * Dp + (q & 15)];
         rb[u] = cur[(uint64_t)(q >> 6) * Rp + r0 + (q & 63)];
     }
     for (uint32_t k0 = 0; k0 < Dp; k0 += DN_KT) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < AL; ++u) {
             const int q = t + 256 * u;
             As[q >> 4][q & 15] = ra[u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int q = t + 256 * u;
             Bs[q >> 6][q & 63] = rb[u];
         }
         __syncthreads();
         if (k0 + DN_KT < Dp) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < AL; ++u) {
                 const int q = t + 256 * u;
                 ra[u] = Ht[(uint64_t)(i0 + (q >> 4)) * Dp + k0 + DN_KT + (q & 15)];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int q = t + 256 * u;
                 rb[u] = cur[(uint64_t)(k0 + DN_KT + (q >> 6)) * Rp + r0 + (q & 63)];
             }
         }
 #pragma unroll
         for (int kk = 0; kk < DN_KT; kk += 4) {
-            double av[2], bv[2];
+            double av[NP], bv[NQ];
 #pragma unroll
-            for (int p = 0; p < 2; ++p) av[p] = As[wr + 16 * p + lr][kk + lk];
+            for (int p = 0; p < NP; ++p) av[p] = As[wr + 16 * p + lr][kk + lk];
 #pragma unroll
-            for (int q = 0; q < 2; ++q) bv[q] = Bs[kk + lk][wc + 16 * q + lr];
+            for (int q = 0; q < NQ; ++q) bv[q] = Bs[kk + lk][wc + 16 * q + lr];
 #pragma unroll
-            for (int p = 0; p < 2; ++p)
+            for (int p = 0; p < NP; ++p)
 #pragma unroll
-                for (int q = 0; q < 2; ++q) acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[p], bv[q], acc[p][q], 0, 0, 0);
+                for (int q = 0; q < NQ; ++q) acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[p], bv[q], acc[p][q], 0, 0, 0);
         }
         __syncthreads();
     }
     double s0 = 0.0, c0 = 0.0, s1 = 0.0, c1 = 0.0;
 #pragma unroll
-    for (int p = 0; p < 2; ++p)
+    for (int p = 0; p < NP; ++p)
 #pragma unroll
-        for (int q = 0; q < 2; ++q)
+        for (int q = 0; q < NQ; ++q)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const uint32_t i = i0 + wr + 16 * p + 4 * v + lk;
