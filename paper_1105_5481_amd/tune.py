@@ -1,7 +1,8 @@
 """Launch-shape autotuner.
 
 The recursion kernels take their work decomposition from the library's launch keys (march
-segments, XCD split, segment direction, store kind, block cap, chunks per thread, batch waves).
+segments, XCD split, segment direction, store kind, block cap, chunks per thread, batch waves,
+two steps per pass).
 The best values depend on the operator class, the lattice shape, R and the precision, so this
 module times candidates on the caller's own operators and keeps the fastest.
 
@@ -37,8 +38,9 @@ CANDIDATES: Dict[str, List[int]] = {
     "max_blocks": [512, 1024, 2048, 4096, 8192],
     "elems_per_thread": [1, 2, 4],
     "wave_mib": [0, 64, 128, 192, 256],
+    "tblock": [0, 1],
 }
-LATTICE_KEYS = ["march_items", "xcd_split", "alternate", "streaming", "max_blocks"]
+LATTICE_KEYS = ["march_items", "xcd_split", "alternate", "streaming", "max_blocks", "tblock"]
 FLAT_KEYS = ["elems_per_thread", "max_blocks"]
 
 
