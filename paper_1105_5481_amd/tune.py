@@ -6,8 +6,9 @@ two steps per pass).
 The best values depend on the operator class, the lattice shape, R and the precision, so this
 module times candidates on the caller's own operators and keeps the fastest.
 
-The time of one recursion step is measured as the difference of two batched solves of K and 2K
-steps (so start vectors, reductions and moments cancel), each taken as the minimum of a few
+The time of one recursion step is measured as the difference of two solves of K and 2K steps
+(so start vectors, reductions and moments cancel; one Hamiltonian runs kpm_moments, several one
+batched solve), each taken as the minimum of a few
 repeats on the current stream with device events.  The keys are tuned one at a time, each over
 its candidate list with the others held at their best value so far (coordinate descent, two
 passes); a change is kept only if it is at least `min_gain` faster.  Only launch keys change:
@@ -28,7 +29,7 @@ import json
 import os
 from typing import Dict, List, Optional, Sequence
 
-from . import Hamiltonian, get_launch, launch_settings, moments_batched
+from . import Hamiltonian, get_launch, launch_settings, moments, moments_batched
 
 CANDIDATES: Dict[str, List[int]] = {
     "march_items": [128, 256, 512, 1024, 2048, 4096],
@@ -81,7 +82,8 @@ def _keys_for(hams: Sequence[Hamiltonian]) -> List[str]:
 
 
 def time_step(hams: Sequence[Hamiltonian], R, vec: int, steps: int = 16, repeats: int = 3) -> float:
-    """Seconds per recursion step of the batched solve of `hams` under the current launch keys."""
+    """Seconds per recursion step of the solve of `hams` (one Hamiltonian: kpm_moments; several: one
+    batched solve) under the current launch keys."""
     import torch
     stream = torch.cuda.current_stream()
 
@@ -90,7 +92,10 @@ def time_step(hams: Sequence[Hamiltonian], R, vec: int, steps: int = 16, repeats
         for _ in range(repeats):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            moments_batched(hams, 2 * K, R, vec, [1] * len(hams), list(range(len(hams))))
+            if len(hams) == 1:     # a single solve runs the single-solve path (kpm_moments)
+                moments(hams[0], 2 * K, R if isinstance(R, int) else R[0], vec, 1, 0)
+            else:
+                moments_batched(hams, 2 * K, R, vec, [1] * len(hams), list(range(len(hams))))
             e1.record(stream)
             e1.synchronize()
             best = min(best, e0.elapsed_time(e1) * 1e-3)
