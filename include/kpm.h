@@ -250,7 +250,8 @@ size_t kpm_ham_bytes(const kpm_ham *h);
  * with kpm_solve_finish as usual.  Results are bitwise equal to the same solve
  * run alone (per-work-item partials).  All members share the recursion
  * precision.  The batch owns a small device table (one hipMalloc in create).
- * Calls on one batch must be serialised and use one stream. */
+ * Calls on one batch must be serialised and use one stream.  kpm_batch_size
+ * returns the number of members (-1 for NULL). */
 typedef struct kpm_batch kpm_batch;
 kpm_status kpm_batch_create(int32_t capacity, kpm_batch **out);
 kpm_status kpm_batch_add(kpm_batch *b, kpm_solve *s);

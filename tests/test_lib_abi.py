@@ -170,3 +170,63 @@ def test_block_placement(L, case, split):
             assert load.max() - load.min() <= whole.max()
     idle = int((m == 0xFFFFFFFF).sum())
     assert idle <= 8 * int(nb.max()) + blocks // 4
+
+
+def test_null_handles_and_bad_sizes_are_rejected(L):
+    """Every entry point checks its handle and size arguments on the host: NULL handles, empty or
+    negative sizes and unknown enum values give KPM_ERR_INVALID_ARG (or a zero size / -1 query)
+    without touching the device; the free functions accept NULL."""
+    INVALID = 1
+    out = ctypes.c_void_p()
+    rem = ctypes.c_int32()
+    inf = float("inf")
+    dummy = ctypes.c_void_p(16)        # never dereferenced: the size checks come first
+    # handles
+    assert L.kpm_solve_begin(None, 16, 4, 0, 1, 0, None, 0, ctypes.byref(out), None) == INVALID
+    assert L.kpm_solve_advance(None, 1, None, ctypes.byref(rem)) == INVALID
+    assert L.kpm_solve_finish(None, dummy, None) == INVALID
+    assert L.kpm_solve_remaining(None, ctypes.byref(rem)) == INVALID
+    assert L.kpm_solve_mode(None) == -1
+    assert L.kpm_update(None, None, 1.0, 0.0, None) == INVALID
+    assert L.kpm_ham_dim(None) == -1
+    assert L.kpm_ham_bytes(None) == 0
+    assert L.kpm_request_bytes(None, 0, 16, 4, 0) == 0
+    assert L.kpm_workspace_bytes_batched(None, 0, None, None, 0) == 0
+    assert L.kpm_moments_batched(None, 0, None, None, 0, None, None, None, 0, None, None) == INVALID
+    assert L.kpm_batch_add(None, None) == INVALID
+    assert L.kpm_batch_remove(None, None) == INVALID
+    assert L.kpm_batch_size(None) == -1
+    assert L.kpm_batch_advance(None, 1, None) == INVALID
+    assert L.kpm_batch_create(0, ctypes.byref(out)) == INVALID
+    assert L.kpm_batch_create(-3, ctypes.byref(out)) == INVALID
+    assert L.kpm_graph_capture_batched(None, 0, None, None, 0, None, None, None, 0, None, None,
+                                       ctypes.byref(out)) == INVALID
+    assert L.kpm_graph_launch(None, None) == INVALID
+    for free in (L.kpm_free, L.kpm_solve_free, L.kpm_batch_free, L.kpm_graph_free):
+        free(None)
+    # sizes and enums of the device-array entry points
+    assert L.kpm_dos(dummy, 0, 1, 64, 1.0, 0.0, dummy, dummy, None) == INVALID      # M = 0
+    assert L.kpm_dos(dummy, 16, 1, 0, 1.0, 0.0, dummy, dummy, None) == INVALID      # K = 0
+    assert L.kpm_dos(dummy, 16, 1, 64, 0.0, 0.0, dummy, dummy, None) == INVALID     # a = 0
+    assert L.kpm_green(None, 16, 0, 0.0, 64, 1.0, 0.0, dummy, dummy, dummy, None) == INVALID
+    assert L.kpm_green(dummy, 0, 0, 0.0, 64, 1.0, 0.0, dummy, dummy, dummy, None) == INVALID
+    assert L.kpm_green(dummy, 16, 0, 0.0, 0, 1.0, 0.0, dummy, dummy, dummy, None) == INVALID
+    assert L.kpm_green(dummy, 16, 7, 0.0, 64, 1.0, 0.0, dummy, dummy, dummy, None) == INVALID   # kernel
+    assert L.kpm_green(dummy, 16, 2, 0.0, 64, 1.0, 0.0, dummy, dummy, dummy, None) == INVALID   # lambda
+    assert L.kpm_green(dummy, 16, 2, 800.0, 64, 1.0, 0.0, dummy, dummy, dummy, None) == INVALID
+    assert L.kpm_green(dummy, 16, 0, 0.0, 64, -1.0, 0.0, dummy, dummy, dummy, None) == INVALID
+    assert L.kpm_dense_workspace_bytes(0, 16, 4) == 0
+    assert L.kpm_dense_workspace_bytes(64, 0, 4) == 0
+    assert L.kpm_dense_workspace_bytes(64, 16, 0) == 0
+    assert L.kpm_dense_moments(None, 64, 1.0, 0.0, 16, 4, 0, 1, 0, dummy, 1 << 20, dummy, None) == INVALID
+    assert L.kpm_dense_moments(dummy, 0, 1.0, 0.0, 16, 4, 0, 1, 0, dummy, 1 << 20, dummy, None) == INVALID
+    assert L.kpm_dense_moments(dummy, 64, 0.0, 0.0, 16, 4, 0, 1, 0, dummy, 1 << 20, dummy, None) == INVALID
+    assert L.kpm_dense_moments(dummy, 64, 1.0, 0.0, 16, 4, 0, 1, 0, dummy, 0, dummy, None) == 6   # workspace
+    assert L.kpm_start_vectors(0, 0, 0, 0, 0, 2, dummy, None) == INVALID             # N = 0
+    assert L.kpm_start_vectors(0, 0, 0, 0, 10, 0, dummy, None) == INVALID            # R = 0
+    assert L.kpm_bounds_lanczos(None, 10, 0, 0.005, -inf, inf, dummy, 1 << 20, dummy, None) == INVALID
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    assert L.kpm_scale_from_bounds(1.0, -1.0, 0.01, ctypes.byref(lo), ctypes.byref(hi)) == INVALID
+    assert L.kpm_scale_from_bounds(-1.0, 1.0, 2.0, ctypes.byref(lo), ctypes.byref(hi)) == INVALID
+    assert L.kpm_scale_from_bounds(-1.0, 1.0, 0.01, None, None) == INVALID
+    assert L.kpm_get_launch(0, None) == INVALID
