@@ -151,9 +151,12 @@ kpm_status kpm_bounds_lanczos(kpm_ham *h, int32_t k, uint64_t seed, double pad, 
  * dot products fused into the same kernel; the moments are formed as in
  * kpm_moments (mu_dev: device array of M doubles).  Real vectors only:
  * vec = KPM_VEC_RADEMACHER or KPM_VEC_UNIT (KPM_ERR_UNSUPPORTED otherwise).
- * H must be symmetric (not checked).  D <= 65536.  workspace_dev:
+ * H must be symmetric (not checked).  D <= 65536.  For D <= 128 the whole
+ * recursion runs in one launch with H~ in on-chip memory, as long as its
+ * per-step dot partials ((M/2 + 1) x ceil(R/16) x ceil(D/16) x 32 bytes) take
+ * at most 256 MiB; otherwise one launch per step.  workspace_dev:
  * kpm_dense_workspace_bytes(D, M, R) bytes, 256-byte aligned (the padded H~,
- * two D x R vector blocks, partials and dots). */
+ * the D x R vector blocks, partials and dots). */
 size_t kpm_dense_workspace_bytes(int64_t D, int32_t M, int32_t R);
 kpm_status kpm_dense_moments(const double *H_dev, int64_t D, double a, double b, int32_t M, int32_t R,
                              int32_t vec, uint64_t seed, uint64_t instance, void *workspace_dev,

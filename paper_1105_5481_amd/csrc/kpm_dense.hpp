@@ -176,8 +176,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
 // same lane supplies for those rows in the next step, so r_{n-1}, r_n and
 // r_{n+1} stay in registers and only the slab of r_n is shared through LDS.
 // H~ must be symmetric: the A operand H~[i][k] is read as H~[k][i], which
-// keeps the LDS reads of a wave on consecutive addresses.  The per-step dot
-// partials of each block go to slot n + 1 of `part` ([K + 1][blocks][4]).
+// keeps the LDS reads of a wave on consecutive addresses.  The products run
+// as 4 independent accumulation chains.  The per-step dot partials are summed
+// per wave only (no block-wide step) and go to slot n + 1 of `part`
+// ([K + 1][blocks][NW][4]).
+// Wave-level sum of two double-double accumulators; lane 0 stores them.
+__device__ __forceinline__ void dn_wave_store(double x0, double x1, double x2, double x3, double *dst)
+{
+    dd a = dd_fast_two_sum(x0, x1), b = dd_fast_two_sum(x2, x3);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        a = dd_add(a, dd{shfl_xor_d(a.hi, off), shfl_xor_d(a.lo, off)});
+        b = dd_add(b, dd{shfl_xor_d(b.hi, off), shfl_xor_d(b.lo, off)});
+    }
+    if ((threadIdx.x & 63) == 0) {
+        dst[0] = a.hi;
+        dst[1] = a.lo;
+        dst[2] = b.hi;
+        dst[3] = b.lo;
+    }
+}
+
 template <int NW>
 __global__ __launch_bounds__(64 * NW) void k_dense_resident(const double *__restrict__ Ht, uint32_t D, uint32_t R,
                                                             int vec, uint64_t seed, uint64_t instance, int32_t K,
@@ -208,21 +227,26 @@ __global__ __launch_bounds__(64 * NW) void k_dense_resident(const double *__rest
         Vs[i * 16 + lr] = re;
         dot2_acc(s0, e0, re, re);
     }
-    block_reduce_store<true, NT>(s0, e0, 0.0, 0.0, part + (size_t)blockIdx.x * 4);
+    const size_t wslot = (size_t)blockIdx.x * NW + w;   // this wave's partial within a slot
+    dn_wave_store(s0, e0, 0.0, 0.0, part + wslot * 4);
     __syncthreads();
     for (int32_t n = 0; n < K; ++n) {
-        dn_d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-        for (uint32_t s = 0; s < Dp / 4; s += 2) {
-            const uint32_t k0 = 4 * s + lk, k1 = 4 * (s + 1) + lk;
-            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(Hs[k0 * Dp + 16 * w + lr], Vs[k0 * 16 + lr], acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(Hs[k1 * Dp + 16 * w + lr], Vs[k1 * 16 + lr], acc1, 0, 0, 0);
+        dn_d4 acc[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c] = dn_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+        for (uint32_t s = 0; s < Dp / 4; s += 4) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const uint32_t k = 4 * (s + c) + lk;
+                acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(Hs[k * Dp + 16 * w + lr], Vs[k * 16 + lr], acc[c], 0, 0, 0);
+            }
         }
         __syncthreads();   // every wave has read the slab of r_n
         double x0 = 0.0, y0 = 0.0, x1 = 0.0, y1 = 0.0;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            double out = acc0[v] + acc1[v];
+            double out = (acc[0][v] + acc[1][v]) + (acc[2][v] + acc[3][v]);
             if (n > 0) out = 2.0 * out - prev[v];
             dot2_acc(x0, y0, out, out);
             dot2_acc(x1, y1, out, cur[v]);
@@ -230,7 +254,7 @@ __global__ __launch_bounds__(64 * NW) void k_dense_resident(const double *__rest
             cur[v] = out;
             Vs[(16 * w + 4 * v + lk) * 16 + lr] = out;
         }
-        block_reduce_store<true, NT>(x0, y0, x1, y1, part + ((size_t)(n + 1) * nblk + blockIdx.x) * 4);
+        dn_wave_store(x0, y0, x1, y1, part + ((size_t)(n + 1) * nblk * NW + wslot) * 4);
         __syncthreads();   // the slab of r_{n+1} is complete
     }
 }

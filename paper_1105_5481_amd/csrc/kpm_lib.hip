@@ -1733,14 +1733,17 @@ constexpr int64_t DENSE_RESIDENT_MAX = 128;   // H~ (FP64) and one vector slab f
 struct DenseLayout {
     bool resident;
     int tm;                // output rows per block of the tiled kernel (64 or 128)
-    uint32_t Dp, Rp, tiles;
+    uint32_t Dp, Rp, blocks, tiles;   // grid; partial sums per step (resident: one per wave)
     int32_t K, P_slots;
     size_t ht_off, v0_off, v1_off, part_off, dots_off, total;
 };
 bool dense_layout(int64_t D, int32_t M, int32_t R, DenseLayout &L)
 {
     if (D < 1 || D > 65536 || M < 1 || R < 1 || R > (1 << 20)) return false;
-    L.resident = g_small && D <= DENSE_RESIDENT_MAX;
+    // the on-chip path keeps every step's per-wave dot partials until the end:
+    // (M/2 + 1) x (R/16 slabs) x (D/16 waves) x 32 bytes, held to 256 MiB
+    const uint64_t res_part = ((uint64_t)(M / 2) + 1) * (uint64_t)((R + 15) / 16) * (uint64_t)((D + 15) / 16) * 32;
+    L.resident = g_small && D <= DENSE_RESIDENT_MAX && res_part <= (256ull << 20);
     const uint32_t q = L.resident ? 16 : DN_TILE;
     L.Dp = (uint32_t)((D + q - 1) / q * q);
     L.Rp = (uint32_t)((R + q - 1) / q * q);
@@ -1748,7 +1751,8 @@ bool dense_layout(int64_t D, int32_t M, int32_t R, DenseLayout &L)
     // 128-row blocks (k_dense_step<., 128>) measured slower at D = 4096 (45.5 vs 52 TFLOP/s)
     // and for D <= 1024; 64 x 64 blocks throughout
     L.tm = DN_TILE;
-    L.tiles = L.resident ? L.Rp / 16 : (L.Dp / L.tm) * (L.Rp / DN_TILE);
+    L.blocks = L.resident ? L.Rp / 16 : (L.Dp / L.tm) * (L.Rp / DN_TILE);
+    L.tiles = L.resident ? L.blocks * (L.Dp / 16) : L.blocks;
     L.K = M / 2;
     L.P_slots = L.resident ? L.K + 1 : std::min(L.K + 1, PSLOTS_MAX);
     const size_t vbytes = L.resident ? 0 : align256((size_t)L.Dp * L.Rp * 8);
@@ -1813,7 +1817,7 @@ kpm_status kpm_dense_moments(const double *H_dev, int64_t D, double a, double b,
         if (hipFuncSetAttribute((const void *)fns[nw - 1], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
             hipSuccess)
             return KPM_ERR_DEVICE;
-        hipLaunchKernelGGL(fns[nw - 1], dim3(L.tiles), dim3(64 * nw), lds, st, Ht, (uint32_t)D, (uint32_t)R, vec, seed,
+        hipLaunchKernelGGL(fns[nw - 1], dim3(L.blocks), dim3(64 * nw), lds, st, Ht, (uint32_t)D, (uint32_t)R, vec, seed,
                            instance, L.K, part);
         e = check_launch();
         if (e == KPM_OK) e = launch_reduce(tab, 1, -1, L.K + 1, st);
