@@ -8,9 +8,10 @@
 // block Dp x Rp, Dp and Rp multiples of 64, so padded rows and columns stay
 // exactly zero through the recursion and add nothing to the dots.
 //
-// One workgroup (4 waves) computes a 64 x 64 block of H~ V_n with the FP64
-// matrix instruction v_mfma_f64_16x16x4 (each wave a 32 x 32 quarter, 2 x 2
-// instruction tiles), staging 64 x 16 slices of H~ and 16 x 64 slices of V_n
+// One workgroup (4 waves) computes a 64 x 64 (or 64 x 32) block of H~ V_n
+// with the FP64 matrix instruction v_mfma_f64_16x16x4 (each wave a quarter of
+// 2 x 2 or 2 x 1 instruction tiles), staging 64 x 16 slices of H~ and 16 x 64
+// (16 x 32) slices of V_n
 // through LDS, and finishes the block in registers: the recursion update,
 // the store of V_{n+1} over V_{n-1}, and the per-block double-double partial
 // sums of <V_{n+1}|V_{n+1}> and <V_{n+1}|V_n>.
@@ -44,16 +45,17 @@ __global__ __launch_bounds__(256) void k_dense_scale(const double *__restrict__ 
 }
 
 // V_0 = xi (R real start vectors of kind vec, column r = vector r) over the
-// output tiles of the step kernel, with the partials of <V_0|V_0> (slot 0).
+// 64 x tn output tiles of the step kernel, with the partials of <V_0|V_0>
+// (slot 0).
 __global__ __launch_bounds__(256) void k_dense_init(uint32_t D, uint32_t Dp, uint32_t R, uint32_t Rp, int vec,
-                                                    uint64_t seed, uint64_t instance, uint32_t tm,
+                                                    uint64_t seed, uint64_t instance, uint32_t tn,
                                                     double *__restrict__ V, double *__restrict__ part)
 {
-    const uint32_t tiles_r = Rp / DN_TILE;
-    const uint32_t i0 = (blockIdx.x / tiles_r) * tm, r0 = (blockIdx.x % tiles_r) * DN_TILE;
+    const uint32_t tiles_r = Rp / tn;
+    const uint32_t i0 = (blockIdx.x / tiles_r) * DN_TILE, r0 = (blockIdx.x % tiles_r) * tn;
     double s = 0.0, c = 0.0;
-    for (uint32_t q = threadIdx.x; q < tm * DN_TILE; q += 256) {
-        const uint32_t i = i0 + q / DN_TILE, r = r0 + q % DN_TILE;
+    for (uint32_t q = threadIdx.x; q < DN_TILE * tn; q += 256) {
+        const uint32_t i = i0 + q / tn, r = r0 + q % tn;
         double re = 0.0, im = 0.0;
         if (i < D && r < R) {
             uint64_t w[4] = {0, 0, 0, 0};
@@ -68,69 +70,70 @@ __global__ __launch_bounds__(256) void k_dense_init(uint32_t D, uint32_t Dp, uin
 
 // One recursion step: next = H~ cur (FIRST) or 2 H~ cur - next, and the
 // partials of <next|next>, <next|cur> for the dots index of this step.
-// The block computes TM x 64 outputs (TM = 64: waves in 2 x 2 quarters of
-// 32 x 32; TM = 128: waves in 4 row bands of 32 x 64, so every A value feeds 4
-// matrix instructions).
+// The block computes 64 x TN outputs with its 4 waves in 2 x 2 quarters of
+// 32 x TN/2 (TN = 64, or 32 to give small products twice the blocks).
 // The register budget is capped for 5 waves per SIMD: at the compiler's own
 // choice (99 VGPRs + 32 AGPRs, 3 waves) the matrix pipe idled a third of the
-// time (D = 4096: 50.7 TFLOP/s; capped: 61.6, no spills).
-template <bool FIRST, int TM>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_dense_step(const double *__restrict__ Ht, const double *__restrict__ cur,
-                                                    double *__restrict__ next, uint32_t Dp, uint32_t Rp,
-                                                    double *__restrict__ part)
+// time (D = 4096: 50.7 TFLOP/s; capped: 61.6, no spills).  (Blocks of 128
+// rows, every A value feeding 4 instructions, measured slower: 45.5 vs 52
+// TFLOP/s at D = 4096.)
+template <bool FIRST, int TN>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_dense_step(
+    const double *__restrict__ Ht, const double *__restrict__ cur, double *__restrict__ next, uint32_t Dp, uint32_t Rp,
+    double *__restrict__ part)
 {
-    constexpr int WR = TM == 128 ? 32 : 32;          // rows per wave
-    constexpr int WC = TM == 128 ? 64 : 32;          // columns per wave
-    constexpr int NP = WR / 16, NQ = WC / 16;        // instruction tiles per wave
-    constexpr int AL = TM * DN_KT / 256;             // A values staged per thread per slice
-    __shared__ double As[TM][DN_KT + 1];
-    __shared__ double Bs[DN_KT][DN_TILE + 2];
-    const uint32_t tiles_r = Rp / DN_TILE;
-    const uint32_t i0 = (blockIdx.x / tiles_r) * TM, r0 = (blockIdx.x % tiles_r) * DN_TILE;
+    constexpr int WC = TN / 2;                       // columns per wave
+    constexpr int NP = 2, NQ = WC / 16;              // instruction tiles per wave
+    constexpr int AL = DN_TILE * DN_KT / 256;        // A values staged per thread per slice
+    constexpr int BL = DN_KT * TN / 256;             // B values staged per thread per slice
+    __shared__ double As[DN_TILE][DN_KT + 1];
+    __shared__ double Bs[DN_KT][TN + 2];
+    const uint32_t tiles_r = Rp / TN;
+    const uint32_t i0 = (blockIdx.x / tiles_r) * DN_TILE, r0 = (blockIdx.x % tiles_r) * TN;
     const int t = threadIdx.x, l = t & 63, w = t >> 6;
-    const int wr = TM == 128 ? 32 * w : (w >> 1) * 32, wc = TM == 128 ? 0 : (w & 1) * 32;
+    const int wr = (w >> 1) * 32, wc = (w & 1) * WC;
     const int lr = l & 15, lk = l >> 4;
     dn_d4 acc[NP][NQ];
 #pragma unroll
     for (int p = 0; p < NP; ++p)
 #pragma unroll
         for (int q = 0; q < NQ; ++q) acc[p][q] = dn_d4{0.0, 0.0, 0.0, 0.0};
-    // the slices H~[i0:i0+TM, k0:k0+16] and cur[k0:k0+16, r0:r0+64]; the next
+    // the slices H~[i0:i0+64, k0:k0+16] and cur[k0:k0+16, r0:r0+TN]; the next
     // slice is loaded into registers while the matrix instructions work on the
     // current one in LDS
-    double ra[AL], rb[4];
+    double ra[AL], rb[BL];
 #pragma unroll
     for (int u = 0; u < AL; ++u) {
         const int q = t + 256 * u;
-        ra[u] = Ht[(uint64_t)(i0 + (q >> 4)) * Dp + (q & 15)];
+        ra[u] = Ht[(uint64_t)(i0 + q / DN_KT) * Dp + (q % DN_KT)];
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < BL; ++u) {
         const int q = t + 256 * u;
-        rb[u] = cur[(uint64_t)(q >> 6) * Rp + r0 + (q & 63)];
+        rb[u] = cur[(uint64_t)(q / TN) * Rp + r0 + (q % TN)];
     }
     for (uint32_t k0 = 0; k0 < Dp; k0 += DN_KT) {
 #pragma unroll
         for (int u = 0; u < AL; ++u) {
             const int q = t + 256 * u;
-            As[q >> 4][q & 15] = ra[u];
+            As[q / DN_KT][q % DN_KT] = ra[u];
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < BL; ++u) {
             const int q = t + 256 * u;
-            Bs[q >> 6][q & 63] = rb[u];
+            Bs[q / TN][q % TN] = rb[u];
         }
         __syncthreads();
         if (k0 + DN_KT < Dp) {
 #pragma unroll
             for (int u = 0; u < AL; ++u) {
                 const int q = t + 256 * u;
-                ra[u] = Ht[(uint64_t)(i0 + (q >> 4)) * Dp + k0 + DN_KT + (q & 15)];
+                ra[u] = Ht[(uint64_t)(i0 + q / DN_KT) * Dp + k0 + DN_KT + (q % DN_KT)];
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < BL; ++u) {
                 const int q = t + 256 * u;
-                rb[u] = cur[(uint64_t)(k0 + DN_KT + (q >> 6)) * Rp + r0 + (q & 63)];
+                rb[u] = cur[(uint64_t)(k0 + DN_KT + q / TN) * Rp + r0 + (q % TN)];
             }
         }
 #pragma unroll

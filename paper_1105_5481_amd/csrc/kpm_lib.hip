@@ -1732,7 +1732,7 @@ namespace {
 constexpr int64_t DENSE_RESIDENT_MAX = 128;   // H~ (FP64) and one vector slab fit one CU's LDS
 struct DenseLayout {
     bool resident;
-    int tm;                // output rows per block of the tiled kernel (64 or 128)
+    uint32_t tn;           // output columns per block of the tiled kernel (64 or 32)
     uint32_t Dp, Rp, blocks, tiles;   // grid; partial sums per step (resident: one per wave)
     int32_t K, P_slots;
     size_t ht_off, v0_off, v1_off, part_off, dots_off, total;
@@ -1748,10 +1748,9 @@ bool dense_layout(int64_t D, int32_t M, int32_t R, DenseLayout &L)
     L.Dp = (uint32_t)((D + q - 1) / q * q);
     L.Rp = (uint32_t)((R + q - 1) / q * q);
     if ((uint64_t)L.Dp * L.Rp >= (1ull << 40)) return false;
-    // 128-row blocks (k_dense_step<., 128>) measured slower at D = 4096 (45.5 vs 52 TFLOP/s)
-    // and for D <= 1024; 64 x 64 blocks throughout
-    L.tm = DN_TILE;
-    L.blocks = L.resident ? L.Rp / 16 : (L.Dp / L.tm) * (L.Rp / DN_TILE);
+    // 64 x 64 output blocks, or 64 x 32 when that leaves fewer than 4 blocks per CU
+    L.tn = ((L.Dp / DN_TILE) * (L.Rp / DN_TILE) < 1024) ? 32 : DN_TILE;
+    L.blocks = L.resident ? L.Rp / 16 : (L.Dp / DN_TILE) * (L.Rp / L.tn);
     L.tiles = L.resident ? L.blocks * (L.Dp / 16) : L.blocks;
     L.K = M / 2;
     L.P_slots = L.resident ? L.K + 1 : std::min(L.K + 1, PSLOTS_MAX);
@@ -1826,7 +1825,7 @@ kpm_status kpm_dense_moments(const double *H_dev, int64_t D, double a, double b,
     }
     if (e == KPM_OK) {
         hipLaunchKernelGGL(k_dense_init, dim3(L.tiles), dim3(256), 0, st, (uint32_t)D, L.Dp, (uint32_t)R, L.Rp, vec, seed,
-                           instance, (uint32_t)L.tm, V[0], part);
+                           instance, L.tn, V[0], part);
         e = check_launch();
     }
     int32_t written = 1, reduced = 0;
@@ -1838,8 +1837,8 @@ kpm_status kpm_dense_moments(const double *H_dev, int64_t D, double a, double b,
         }
         double *pslot = part + (size_t)((n + 1) % L.P_slots) * L.tiles * 4;
         typedef void (*step_fn)(const double *, const double *, double *, uint32_t, uint32_t, double *);
-        const step_fn f = L.tm == 128 ? (n == 0 ? k_dense_step<true, 128> : k_dense_step<false, 128>)
-                                      : (n == 0 ? k_dense_step<true, 64> : k_dense_step<false, 64>);
+        const step_fn f = L.tn == 32 ? (n == 0 ? k_dense_step<true, 32> : k_dense_step<false, 32>)
+                                     : (n == 0 ? k_dense_step<true, 64> : k_dense_step<false, 64>);
         hipLaunchKernelGGL(f, dim3(L.tiles), dim3(256), 0, st, Ht, V[n & 1], V[(n + 1) & 1], L.Dp, L.Rp, pslot);
         e = check_launch();
         written += 1;

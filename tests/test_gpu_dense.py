@@ -47,7 +47,9 @@ def test_e1_lattice_dense_equals_oracle_and_stencil():
     assert np.abs(mu - sten).max() <= TOL
 
 
-@pytest.mark.parametrize("D,R,M", [(300, 70, 101), (64, 1, 40), (129, 65, 64), (100, 37, 77), (128, 48, 300)])
+# (2048, 2048, 6): 1024 output blocks, so the product runs on 64 x 64 blocks; the others on 64 x 32
+@pytest.mark.parametrize("D,R,M", [(300, 70, 101), (64, 1, 40), (129, 65, 64), (100, 37, 77), (128, 48, 300),
+                                   (2048, 2048, 6)])
 def test_random_dense_matches_oracle(D, R, M):
     import torch
     H = _goe(D, D + R)
