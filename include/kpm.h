@@ -328,12 +328,13 @@ kpm_status kpm_start_vectors(int32_t vec, int32_t complex_layout, uint64_t seed,
  *                                compute unit runs entirely in one workgroup (one launch)
  *   KPM_LAUNCH_STREAMING         march kernels: 1 = r_{n-1} read / r_{n+1} written with
  *                                non-temporal hints, 0 = cached, 2 (default) = cached when
- *                                vectors and operator take at most 192 MiB (they then stay
- *                                in the 256 MiB Infinity Cache between steps), else 1
+ *                                vectors and operator take at most 256 MiB (they then
+ *                                largely stay in the 256 MiB Infinity Cache between
+ *                                steps), else 1
  *   KPM_LAUNCH_WAVE_MIB          kpm_moments_batched: instances run in waves, each wave
  *                                taking the next instances (in argument order) while their
  *                                vectors and operators total at most this many MiB (default
- *                                192, so a wave stays in the Infinity Cache); a wave runs all
+ *                                224, so a wave stays in the Infinity Cache); a wave runs all
  *                                its recursion steps before the next starts.  0 = one wave
  *   KPM_LAUNCH_TBLOCK            1 (default): solves on 2D lattices with real hopping (C <= 64
  *                                chunks per site dividing 512, L_x >= 512/C) run two

@@ -28,9 +28,12 @@ int g_xcd_split = 0;                    // 0 automatic, 1 by column tiles, 2 by 
 int g_alternate = 1;                    // march: odd segments walk downwards
 int g_small = 1;                        // solves whose two vector blocks fit in LDS run in one workgroup
 int g_streaming = 2;                    // march: 0 cached, 1 non-temporal access of r_{n-1}/r_{n+1}, 2 by size
-int g_wave_mib = 192;                   // batched solves: vectors + operators per wave (MiB), 0 = one wave
+int g_wave_mib = 224;                   // batched solves: vectors + operators per wave (MiB), 0 = one wave
 int g_tblock = 1;                       // 2D real lattices: two recursion steps per pass (temporal blocking)
-constexpr uint64_t CACHE_RESIDENT_BYTES = 192ull << 20;   // below this the state stays in the 256 MiB Infinity Cache
+// Up to this much state (vectors + operator) r_{n+1} is stored cached, to be read back as r_n
+// from the 256 MiB Infinity Cache; measured on 64 x 64 x L_z spin lattices (c64, R = 32),
+// cached stores still win at 251 MiB (5.46 vs 5.00 TB/s; 234 MiB: 6.22 vs 5.01).
+constexpr uint64_t CACHE_RESIDENT_BYTES = 256ull << 20;
 
 // Dynamic LDS one workgroup may use for the small-solve path (0 if no device).
 size_t small_lds_limit()

@@ -38,7 +38,7 @@ CANDIDATES: Dict[str, List[int]] = {
     "streaming": [0, 1, 2],
     "max_blocks": [512, 1024, 2048, 4096, 8192],
     "elems_per_thread": [1, 2, 4],
-    "wave_mib": [0, 64, 128, 192, 256],
+    "wave_mib": [0, 128, 192, 224, 256],
     "tblock": [0, 1],
 }
 LATTICE_KEYS = ["march_items", "xcd_split", "alternate", "streaming", "max_blocks", "tblock"]
