@@ -172,17 +172,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
 // ---------------------------------------------------------------------------
 // small H~ (D <= 128): the whole recursion on chip, one launch
 // ---------------------------------------------------------------------------
-// H~ lives in LDS (Dp x Dp, Dp = 16 NW) and each block owns a 16-column slab
-// of the vectors for all steps: wave w computes rows 16w .. 16w + 15 of
-// H~ V_n with Dp/4 matrix instructions; the 4 results a lane receives
-// (rows 16w + 4v + l/16, column l % 16) are exactly the B-operand values the
-// same lane supplies for those rows in the next step, so r_{n-1}, r_n and
-// r_{n+1} stay in registers and only the slab of r_n is shared through LDS.
-// H~ must be symmetric: the A operand H~[i][k] is read as H~[k][i], which
-// keeps the LDS reads of a wave on consecutive addresses.  The products run
-// as 4 independent accumulation chains.  The per-step dot partials are summed
-// per wave only (no block-wide step) and go to slot n + 1 of `part`
+// Each block owns a 16-column slab of the vectors for all steps (Dp = 16 NW):
+// wave w computes rows 16w .. 16w + 15 of H~ V_n with Dp/4 matrix
+// instructions, whose A operands (the Dp/4 values of H~ a lane supplies) it
+// loads once into registers and keeps for the whole solve; the 4 results a
+// lane receives (rows 16w + 4v + l/16, column l % 16) are exactly the
+// B-operand values the same lane supplies for those rows in the next step, so
+// r_{n-1}, r_n and r_{n+1} stay in registers and only the slab of r_n is
+// shared through LDS.  H~ must be symmetric: the A operand H~[i][k] is read as
+// H~[k][i] (consecutive addresses across a wave).  The products run as 4
+// independent accumulation chains.  The per-step dot partials are summed per
+// wave only (no block-wide step) and go to slot n + 1 of `part`
 // ([K + 1][blocks][NW][4]).
+
 // Wave-level sum of two double-double accumulators; lane 0 stores them.
 __device__ __forceinline__ void dn_wave_store(double x0, double x1, double x2, double x3, double *dst)
 {
@@ -207,14 +209,14 @@ __global__ __launch_bounds__(64 * NW) void k_dense_resident(const double *__rest
 {
     extern __shared__ double lds[];
     constexpr uint32_t Dp = 16 * NW;
-    constexpr int NT = 64 * NW;
-    double *Hs = lds;              // Dp x Dp
-    double *Vs = lds + Dp * Dp;    // Dp x 16
+    double *Vs = lds;              // Dp x 16
     const int t = threadIdx.x, l = t & 63, w = t >> 6;
     const int lr = l & 15, lk = l >> 4;
     const uint32_t nblk = gridDim.x;
     const uint32_t col = blockIdx.x * 16 + lr;
-    for (uint32_t q = t; q < Dp * Dp; q += NT) Hs[q] = Ht[q];
+    double ha[Dp / 4];   // this lane's A operands: H~[4 s + l/16][16 w + l % 16]
+#pragma unroll
+    for (uint32_t s = 0; s < Dp / 4; ++s) ha[s] = Ht[(4 * s + lk) * Dp + 16 * w + lr];
     double cur[4], prev[4] = {0.0, 0.0, 0.0, 0.0};
     double s0 = 0.0, e0 = 0.0;
 #pragma unroll
@@ -237,12 +239,12 @@ __global__ __launch_bounds__(64 * NW) void k_dense_resident(const double *__rest
         dn_d4 acc[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[c] = dn_d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 2
+#pragma unroll
         for (uint32_t s = 0; s < Dp / 4; s += 4) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const uint32_t k = 4 * (s + c) + lk;
-                acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(Hs[k * Dp + 16 * w + lr], Vs[k * 16 + lr], acc[c], 0, 0, 0);
+                acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ha[s + c], Vs[k * 16 + lr], acc[c], 0, 0, 0);
             }
         }
         __syncthreads();   // every wave has read the slab of r_n

@@ -1815,7 +1815,7 @@ kpm_status kpm_dense_moments(const double *H_dev, int64_t D, double a, double b,
                                       k_dense_resident<4>, k_dense_resident<5>, k_dense_resident<6>,
                                       k_dense_resident<7>, k_dense_resident<8>};
         const int nw = (int)(L.Dp / 16);
-        const size_t lds = ((size_t)L.Dp * L.Dp + (size_t)L.Dp * 16) * 8;
+        const size_t lds = (size_t)L.Dp * 16 * 8;
         if (hipFuncSetAttribute((const void *)fns[nw - 1], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
             hipSuccess)
             return KPM_ERR_DEVICE;
