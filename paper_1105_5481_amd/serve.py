@@ -161,15 +161,24 @@ class Server:
                 break                                   # first come, first served
             self.pending.popleft()
             t_admit = self.now()
-            if req.scale is not None:
-                a, b = req.scale
-            elif req.bounds == "lanczos":
-                a, b = lanczos_scale(req.op, req.lanczos_k, req.eps, device=self.device)
-            else:
-                lo, hi = gershgorin(req.op, self.device)
-                a, b = scale_from_bounds(lo, hi, req.eps)
-            ham = Hamiltonian(req.op, a, b, self.prec, self.device)
-            solve = Solve(ham, req.M, req.R, req.vec, req.seed, req.instance)
+            ham = solve = None
+            try:
+                if req.scale is not None:
+                    a, b = req.scale
+                elif req.bounds == "lanczos":
+                    a, b = lanczos_scale(req.op, req.lanczos_k, req.eps, device=self.device)
+                else:
+                    lo, hi = gershgorin(req.op, self.device)
+                    a, b = scale_from_bounds(lo, hi, req.eps)
+                ham = Hamiltonian(req.op, a, b, self.prec, self.device)
+                solve = Solve(ham, req.M, req.R, req.vec, req.seed, req.instance)
+            except KPMError as e:          # e.g. a CSR structure the device check rejects
+                if solve is not None:
+                    solve.close()
+                if ham is not None:
+                    ham.free()
+                self._finish_result(req, "error", t_admit=t_admit, message=str(e))
+                continue
             live = _Live(req=req, bytes=need, ham=ham, solve=solve, t_admit=t_admit)
             self.used += need
             if solve.remaining > 0:

@@ -79,12 +79,19 @@ def test_admission_rejects_oversize_and_isolates_failures():
     lo, hi = oracle.gershgorin_lattice(2, (96, 96), 1.0, 0, reqs[0].op.onsite, None)
     a, b = oracle.scale_from_bounds(lo, hi, 0.01)
     bad = KPMRequest(op=reqs[0].op, M=256, R=8, seed=5, scale=(0.45 * a, b), arrival=1, rid=11)
+    # a CSR whose last column index is out of range: the device structure check rejects it
+    csr = wl.lattice_to_csr(wl.square_lattice(10, W=1.0, seed=3))
+    col = csr.col.copy()
+    col[-1] = csr.n
+    broken = KPMRequest(op=wl.CSR(n=csr.n, row_ptr=csr.row_ptr, col=col, val_re=csr.val_re), M=32, R=4, arrival=1,
+                        rid=12)
     srv = Server(prec=kpm.F32, max_active=8, chunk=16, hbm_budget=256 << 20)
-    res = srv.run(reqs + [big, bad], clock="chunks")
+    res = srv.run(reqs + [big, bad, broken], clock="chunks")
     srv.close()
     st = {r.rid: r.status for r in res}
     assert st[10] == "oom"
     assert st[11] == "bounds"
+    assert st[12] == "error"
     for req in reqs:
         r = [x for x in res if x.rid == req.rid][0]
         assert r.status == "ok"
