@@ -8,6 +8,8 @@ library is missing, every call raises KPMError: there is no fallback.
 from __future__ import annotations
 
 import ctypes
+import functools
+import inspect
 import os
 from typing import List, Optional, Sequence
 
@@ -128,6 +130,25 @@ def _stream(stream) -> ctypes.c_void_p:
     return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
 
 
+def _stream_scoped(fn):
+    """Run `fn` with its `stream` argument (when given) as torch's current stream, so the tensors it
+    allocates and the torch operations it issues are ordered with its library calls on that stream
+    (a torch.cuda.Stream, or a raw hipStream_t handle as an int)."""
+    sig = inspect.signature(fn)
+
+    @functools.wraps(fn)
+    def wrapper(*args, **kwargs):
+        stream = sig.bind_partial(*args, **kwargs).arguments.get("stream")
+        if stream is None:
+            return fn(*args, **kwargs)
+        torch = _torch()
+        if not isinstance(stream, torch.cuda.Stream):
+            stream = torch.cuda.ExternalStream(int(stream))
+        with torch.cuda.stream(stream):
+            return fn(*args, **kwargs)
+    return wrapper
+
+
 def _dev(x, dtype, device):
     torch = _torch()
     if x is None:
@@ -175,17 +196,19 @@ def scale_from_bounds(e_lo: float, e_hi: float, eps: float = 0.01):
     return a.value, b.value
 
 
+@_stream_scoped
 def gershgorin(op, device="cuda", stream=None):
     """(E_lo, E_hi) of a Lattice or CSR, computed on the device in FP64."""
     torch = _torch()
     d, keep = _desc_for(op, device)
     out = torch.empty(2, dtype=torch.float64, device=device)
     _check(lib().kpm_bounds_gershgorin(ctypes.byref(d), _ptr(out), _stream(stream)), "kpm_bounds_gershgorin")
-    torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+    torch.cuda.current_stream().synchronize()
     lo, hi = out.tolist()
     return lo, hi
 
 
+@_stream_scoped
 def lanczos_bounds(ham: "Hamiltonian", k: int = 100, seed: int = 0, pad: float = 0.005, clamp="gershgorin",
                    stream=None) -> dict:
     """Spectral interval of H from k Lanczos steps on the FP64 operator `ham` (kpm_bounds_lanczos):
@@ -210,6 +233,7 @@ def lanczos_bounds(ham: "Hamiltonian", k: int = 100, seed: int = 0, pad: float =
             "beta": o[8 + k:8 + 2 * k].copy()}
 
 
+@_stream_scoped
 def lanczos_scale(op, k: int = 100, eps: float = 0.01, pad: float = 0.005, seed: int = 0, device="cuda",
                   stream=None):
     """(a, b) of Eq. (tilde) from the Lanczos interval of `op` (clipped to Gershgorin), with the
@@ -225,6 +249,7 @@ def lanczos_scale(op, k: int = 100, eps: float = 0.01, pad: float = 0.005, seed:
 class Hamiltonian:
     """The scaled operator H~ = (H - b)/a of Eq. (tilde), resident in device memory."""
 
+    @_stream_scoped
     def __init__(self, op, a: float, b: float, prec: int = F64, device="cuda", stream=None):
         self.op, self.a, self.b, self.prec, self.device = op, float(a), float(b), int(prec), device
         d, keep = _desc_for(op, device)
@@ -233,9 +258,10 @@ class Hamiltonian:
                "kpm_build")
         self._h = h
         # the descriptor's arrays must live until the build kernel has run
-        (stream or _torch().cuda.current_stream()).synchronize()
+        _torch().cuda.current_stream().synchronize()
         del keep
 
+    @_stream_scoped
     def update(self, op, a: float, b: float, stream=None, keep_inputs: bool = False):
         """Re-prepare H~ from new inputs of the same shape in place (no allocation).  The input
         tensors are returned when keep_inputs is set (they must outlive the enqueued kernel);
@@ -245,7 +271,7 @@ class Hamiltonian:
         self.op, self.a, self.b = op, float(a), float(b)
         if keep_inputs:
             return keep
-        (stream or _torch().cuda.current_stream()).synchronize()
+        _torch().cuda.current_stream().synchronize()
         return None
 
     @property
@@ -290,6 +316,7 @@ def _workspace(nbytes: int, device, workspace=None):
     return torch.empty(nbytes, dtype=torch.uint8, device=device)
 
 
+@_stream_scoped
 def moments(ham: Hamiltonian, M: int, R: int, vec: int = VEC_RADEMACHER, seed: int = 0, instance: int = 0,
             stream=None, out=None, workspace=None):
     """mu_0..mu_{M-1} (device FP64 tensor) averaged over R start vectors."""
@@ -302,6 +329,7 @@ def moments(ham: Hamiltonian, M: int, R: int, vec: int = VEC_RADEMACHER, seed: i
     return mu
 
 
+@_stream_scoped
 def moments_batched(hams: Sequence[Hamiltonian], M, R, vec: int = VEC_RADEMACHER, seeds=None, instances=None,
                     stream=None, outs=None, workspace=None) -> List:
     torch = _torch()
@@ -373,6 +401,7 @@ class BatchedGraph:
 class Solve:
     """A chunked solve: begin -> advance(k) ... -> finish; the vector state stays in `workspace`."""
 
+    @_stream_scoped
     def __init__(self, ham: Hamiltonian, M: int, R: int, vec: int = VEC_RADEMACHER, seed: int = 0,
                  instance: int = 0, stream=None, workspace=None):
         self.ham, self.M = ham, M
@@ -389,11 +418,13 @@ class Solve:
         _check(lib().kpm_solve_remaining(self._s, ctypes.byref(rem)), "kpm_solve_remaining")
         return rem.value
 
+    @_stream_scoped
     def advance(self, steps: int, stream=None) -> int:
         rem = ctypes.c_int32()
         _check(lib().kpm_solve_advance(self._s, steps, _stream(stream), ctypes.byref(rem)), "kpm_solve_advance")
         return rem.value
 
+    @_stream_scoped
     def finish(self, out=None, stream=None):
         torch = _torch()
         mu = out if out is not None else torch.empty(self.M, dtype=torch.float64, device=self.ham.device)
@@ -429,6 +460,7 @@ class Batch:
         _check(lib().kpm_batch_remove(self._b, solve._s), "kpm_batch_remove")
         self.members.remove(solve)
 
+    @_stream_scoped
     def advance(self, steps: int, stream=None):
         _check(lib().kpm_batch_advance(self._b, steps, _stream(stream)), "kpm_batch_advance")
 
@@ -467,6 +499,7 @@ def request_bytes(op, prec: int, M: int, R: int, vec: int) -> int:
     return int(n)
 
 
+@_stream_scoped
 def dos(mu, K: int, a: float, b: float, jackson: bool = True, stream=None):
     """(omega, rho) device tensors of Eq. (fKPM) on K Chebyshev points."""
     torch = _torch()
@@ -478,6 +511,7 @@ def dos(mu, K: int, a: float, b: float, jackson: bool = True, stream=None):
     return om, rho
 
 
+@_stream_scoped
 def dense_moments(H, a: float, b: float, M: int, R: int, vec: int = VEC_RADEMACHER, seed: int = 0, instance: int = 0,
                   stream=None, out=None, workspace=None):
     """Moments of a dense real symmetric H (a D x D float64 device tensor, row-major) on the matrix
@@ -497,6 +531,7 @@ def dense_moments(H, a: float, b: float, M: int, R: int, vec: int = VEC_RADEMACH
     return mu
 
 
+@_stream_scoped
 def green(mu, K: int, a: float, b: float, kernel: int = KERNEL_LORENTZ, lam: float = 4.0, stream=None):
     """(omega, G) device tensors (G complex128) of the Green's function <xi|(omega + i0 - H)^{-1}|xi>
     from the moments of xi (kpm_green) on K Chebyshev points."""
@@ -510,6 +545,7 @@ def green(mu, K: int, a: float, b: float, kernel: int = KERNEL_LORENTZ, lam: flo
     return om, torch.complex(gre, gim)
 
 
+@_stream_scoped
 def site_moments(ham: "Hamiltonian", sites, M: int, stream=None) -> List:
     """Moments <i|T_n(H~)|i> of the local DoS at each site i (unit start vector e_i): one batched
     solve with R = 1 per site (KPM_VEC_UNIT with instance = i)."""
@@ -522,6 +558,7 @@ def site_moments(ham: "Hamiltonian", sites, M: int, stream=None) -> List:
     return moments_batched([ham] * len(sites), M, 1, VEC_UNIT, [0] * len(sites), sites, stream=stream)
 
 
+@_stream_scoped
 def ldos(ham: "Hamiltonian", sites, M: int, K: Optional[int] = None, jackson: bool = True, stream=None):
     """Local DoS rho_i(omega) at each site: (omega [K], rho [len(sites), K]) device tensors."""
     torch = _torch()
@@ -535,6 +572,7 @@ def ldos(ham: "Hamiltonian", sites, M: int, K: Optional[int] = None, jackson: bo
     return om, torch.stack(rows) if rows else None
 
 
+@_stream_scoped
 def site_green(ham: "Hamiltonian", sites, M: int, K: Optional[int] = None, kernel: int = KERNEL_LORENTZ,
                lam: float = 4.0, stream=None):
     """Site-diagonal Green's functions G_ii(omega + i0): (omega [K], G [len(sites), K] complex)."""
@@ -549,6 +587,7 @@ def site_green(ham: "Hamiltonian", sites, M: int, K: Optional[int] = None, kerne
     return om, torch.stack(rows) if rows else None
 
 
+@_stream_scoped
 def start_vectors(vec: int, complex_layout: bool, seed: int, instance: int, N: int, R: int, device="cuda",
                   stream=None):
     torch = _torch()
