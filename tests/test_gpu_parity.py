@@ -46,7 +46,33 @@ def _cases():
     c.append(("unit_trace_6x6", wl.square_lattice(6, W=2.0, seed=12), 50, 36, wl.VEC_UNIT))
     for M in (1, 2, 3):
         c.append((f"tiny_M{M}", wl.square_lattice(9, W=1.0, seed=13), M, 3, wl.VEC_RADEMACHER))
+    c.append(("square_1x1_all_self", wl.Lattice(dim=2, L=(1, 1, 1), t=1.0, onsite=np.array([0.3])), 20, 2,
+              wl.VEC_RADEMACHER))
+    c.append(("spin3d_5_R1_phase", wl.spin_cubic_lattice(5, seed=14), 30, 1, wl.VEC_PHASE))
+    c.append(("csr_empty_rows", _csr_with_empty_rows(), 40, 3, wl.VEC_PHASE))
     return c
+
+
+def _csr_with_empty_rows():
+    """A 64 x 64 complex Hermitian matrix acting on 50 of the indices; the other 14 rows (and
+    columns) hold no entries at all."""
+    g = np.random.default_rng(15)
+    n, live = 64, np.sort(g.choice(64, size=50, replace=False))
+    A = np.zeros((n, n), complex)
+    for i in live:
+        for j in g.choice(live, size=4, replace=False):
+            v = complex(g.normal(), g.normal() if i != j else 0.0)
+            A[i, j] += v
+            A[j, i] += np.conj(v)
+    rows, cols = np.nonzero(A)
+    order = np.lexsort((cols, rows))
+    rows, cols = rows[order], cols[order]
+    row_ptr = np.zeros(n + 1, np.int64)
+    np.add.at(row_ptr, rows + 1, 1)
+    row_ptr = np.cumsum(row_ptr)
+    vals = A[rows, cols]
+    return wl.CSR(n=n, row_ptr=row_ptr, col=cols.astype(np.int32), val_re=np.ascontiguousarray(vals.real),
+                  val_im=np.ascontiguousarray(vals.imag))
 
 
 CASES = _cases()
