@@ -185,23 +185,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
 // wave only (no block-wide step) and go to slot n + 1 of `part`
 // ([K + 1][blocks][NW][4]).
 
-// Wave-level sum of two double-double accumulators; lane 0 stores them.
-__device__ __forceinline__ void dn_wave_store(double x0, double x1, double x2, double x3, double *dst)
-{
-    dd a = dd_fast_two_sum(x0, x1), b = dd_fast_two_sum(x2, x3);
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        a = dd_add(a, dd{shfl_xor_d(a.hi, off), shfl_xor_d(a.lo, off)});
-        b = dd_add(b, dd{shfl_xor_d(b.hi, off), shfl_xor_d(b.lo, off)});
-    }
-    if ((threadIdx.x & 63) == 0) {
-        dst[0] = a.hi;
-        dst[1] = a.lo;
-        dst[2] = b.hi;
-        dst[3] = b.lo;
-    }
-}
-
 template <int NW>
 __global__ __launch_bounds__(64 * NW) void k_dense_resident(const double *__restrict__ Ht, uint32_t D, uint32_t R,
                                                             int vec, uint64_t seed, uint64_t instance, int32_t K,
@@ -233,7 +216,7 @@ __global__ __launch_bounds__(64 * NW) void k_dense_resident(const double *__rest
         dot2_acc(s0, e0, re, re);
     }
     const size_t wslot = (size_t)blockIdx.x * NW + w;   // this wave's partial within a slot
-    dn_wave_store(s0, e0, 0.0, 0.0, part + wslot * 4);
+    wave_reduce_store<true>(s0, e0, 0.0, 0.0, part + wslot * 4);
     __syncthreads();
     for (int32_t n = 0; n < K; ++n) {
         dn_d4 acc[4];
@@ -259,7 +242,7 @@ __global__ __launch_bounds__(64 * NW) void k_dense_resident(const double *__rest
             cur[v] = out;
             Vs[(16 * w + 4 * v + lk) * 16 + lr] = out;
         }
-        dn_wave_store(x0, y0, x1, y1, part + ((size_t)(n + 1) * nblk * NW + wslot) * 4);
+        wave_reduce_store<true>(x0, y0, x1, y1, part + ((size_t)(n + 1) * nblk * NW + wslot) * 4);
         __syncthreads();   // the slab of r_{n+1} is complete
     }
 }

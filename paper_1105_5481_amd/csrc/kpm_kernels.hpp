@@ -213,12 +213,12 @@ template <> struct Dots<float> {
     static constexpr bool DD = false;
 };
 
-// Sum (x0 + x1, x2 + x3) over the block in a fixed order; thread 0 stores
-// the four doubles (hi, lo, hi, lo) at dst.
-template <bool DD, int NT = BLOCK>
-__device__ __forceinline__ void block_reduce_store(double x0, double x1, double x2, double x3, double *dst)
+// Sum (x0 + x1, x2 + x3) over the wavefront: every lane receives the sums,
+// as double-double pairs (x0, x1), (x2, x3) when DD, else in x0 and x2 with
+// x1 = x3 = 0.
+template <bool DD>
+__device__ __forceinline__ void wave_reduce(double &x0, double &x1, double &x2, double &x3)
 {
-    __shared__ double red[NT / 64][4];
     if (DD) {
         dd a = dd_fast_two_sum(x0, x1), b = dd_fast_two_sum(x2, x3);
 #pragma unroll
@@ -238,6 +238,26 @@ __device__ __forceinline__ void block_reduce_store(double x0, double x1, double 
         x1 = 0.0;
         x3 = 0.0;
     }
+}
+
+// The wavefront's sums of (x0 + x1, x2 + x3); lane 0 stores the four doubles
+// (hi, lo, hi, lo) at dst.
+template <bool DD>
+__device__ __forceinline__ void wave_reduce_store(double x0, double x1, double x2, double x3, double *dst)
+{
+    wave_reduce<DD>(x0, x1, x2, x3);
+    if ((threadIdx.x & 63) == 0) {
+        dst[0] = x0; dst[1] = x1; dst[2] = x2; dst[3] = x3;
+    }
+}
+
+// Sum (x0 + x1, x2 + x3) over the block in a fixed order; thread 0 stores
+// the four doubles (hi, lo, hi, lo) at dst.
+template <bool DD, int NT = BLOCK>
+__device__ __forceinline__ void block_reduce_store(double x0, double x1, double x2, double x3, double *dst)
+{
+    __shared__ double red[NT / 64][4];
+    wave_reduce<DD>(x0, x1, x2, x3);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (lane == 0) {
         red[w][0] = x0; red[w][1] = x1; red[w][2] = x2; red[w][3] = x3;
@@ -725,9 +745,12 @@ __global__ __launch_bounds__(BLOCK) void k_step_flat(const Inst *__restrict__ ta
 // ---------------------------------------------------------------------------
 // Both vector blocks live in LDS (2 * N * C * 16 bytes <= the LDS of one CU),
 // so the recursion never touches HBM; one block per instance, all steps in one
-// launch, the block barrier of the per-step dot reduction separating steps.
-// The per-step dots go straight to the instance's dots array.
+// launch, one block barrier between steps.  The per-step dots are summed per
+// wave only: partial slot n + 1 holds SMALL_WAVES entries (a block-wide sum
+// each step, whose last part one thread does alone, took about two thirds of
+// the solve), reduced by k_reduce after the launch.
 constexpr int SMALL_BLOCK = 1024;
+constexpr int SMALL_WAVES = SMALL_BLOCK / 64;
 
 template <typename S, int OPK>
 __device__ __forceinline__ typename V16<S>::T small_elem(const Inst &I, uint32_t e, const typename V16<S>::T *cur,
@@ -822,6 +845,7 @@ __global__ __launch_bounds__(SMALL_BLOCK) void k_solve_small(const Inst *__restr
     T *b1 = b0 + I.nel;
     S hop = 0;
     if (OPK == OP_REAL2 || OPK == OP_REAL3) hop = Mem<S, false>::lds(I.hop, 0);
+    const uint32_t w = threadIdx.x >> 6;
     {
         Dots<S> acc;
         for (uint32_t e = threadIdx.x; e < I.nel; e += SMALL_BLOCK) {
@@ -830,8 +854,9 @@ __global__ __launch_bounds__(SMALL_BLOCK) void k_solve_small(const Inst *__restr
             b0[e] = v;
             acc.norm_only(v);
         }
-        block_reduce_store<Dots<S>::DD, SMALL_BLOCK>(acc.s0, acc.c0, acc.s1, acc.c1, I.dots);
+        wave_reduce_store<Dots<S>::DD>(acc.s0, acc.c0, acc.s1, acc.c1, I.partial + (size_t)w * 4);
     }
+    __syncthreads();   // r_0 complete
     for (int32_t n = 0; n < I.K; ++n) {
         const T *cur = (n & 1) ? b1 : b0;
         T *nxt = (n & 1) ? b0 : b1;
@@ -842,8 +867,10 @@ __global__ __launch_bounds__(SMALL_BLOCK) void k_solve_small(const Inst *__restr
             nxt[e] = out;
             acc.add(out, cur[e]);
         }
-        // the reduction's barriers also order this step's LDS writes before the next step's reads
-        block_reduce_store<Dots<S>::DD, SMALL_BLOCK>(acc.s0, acc.c0, acc.s1, acc.c1, I.dots + (size_t)(n + 1) * 4);
+        wave_reduce_store<Dots<S>::DD>(acc.s0, acc.c0, acc.s1, acc.c1,
+                                       I.partial + ((size_t)(n + 1) * SMALL_WAVES + w) * 4);
+        // step n's LDS writes before step n + 1 reads them, and its reads before they are overwritten
+        __syncthreads();
     }
 }
 
@@ -854,7 +881,7 @@ __global__ __launch_bounds__(SMALL_BLOCK) void k_solve_small(const Inst *__restr
 __global__ __launch_bounds__(BLOCK) void k_reduce(const Inst *__restrict__ tab, int32_t klo, int32_t nk)
 {
     const Inst *I = tab + blockIdx.y;
-    if ((int32_t)blockIdx.x >= nk || I->mode == MODE_SMALL) return;   // small solves write their dots directly
+    if ((int32_t)blockIdx.x >= nk) return;
     const int32_t idx = I->step0 + 1 + klo + (int32_t)blockIdx.x;
     if (idx < 0 || idx > I->K) return;
     const double *p = I->partial + (size_t)(idx % I->pslots) * I->tiles * 4;
@@ -870,7 +897,7 @@ __global__ __launch_bounds__(BLOCK) void k_reduce(const Inst *__restrict__ tab, 
 __global__ __launch_bounds__(BLOCK) void k_reduce_ranges(const Inst *__restrict__ tab)
 {
     const Inst *I = tab + blockIdx.y;
-    if ((int32_t)blockIdx.x >= I->red_n || I->mode == MODE_SMALL) return;
+    if ((int32_t)blockIdx.x >= I->red_n) return;
     const int32_t idx = I->red_lo + (int32_t)blockIdx.x;
     if (idx < 0 || idx > I->K) return;
     const double *p = I->partial + (size_t)(idx % I->pslots) * I->tiles * 4;

@@ -538,7 +538,7 @@ bool make_plan(const kpm_ham *h, int32_t M, int32_t R, int32_t vec, Plan &p, boo
     p.nbuf = 2;
     if (g_small && small_bytes <= small_lds_limit()) {
         p.mode = MODE_SMALL;
-        p.tiles = 1;
+        p.tiles = SMALL_WAVES;   // per-wave dot partials
         p.xcd = 0;
     } else if (allow_tb && g_tblock && g_march && h->opk == OP_REAL2 && p.C <= TB_BLOCK / 8 && TB_BLOCK % p.C == 0 &&
                h->L[0] >= TB_BLOCK / p.C && h->L[1] >= 4) {
@@ -591,7 +591,9 @@ bool make_plan(const kpm_ham *h, int32_t M, int32_t R, int32_t vec, Plan &p, boo
     p.dots_bytes = align256((size_t)(p.K + 1) * 4 * sizeof(double));
     p.buf_bytes = align256((size_t)h->N * p.Rs * p.esz);
     if (p.mode == MODE_SMALL) {
-        p.part_bytes = 0;
+        // one launch runs every step: a partial slot per step, reduced afterwards
+        p.P_slots = p.K + 1;
+        p.part_bytes = align256((size_t)p.P_slots * p.tiles * 4 * sizeof(double));
         p.buf_bytes = 0;
         p.nb = 1;
     }
@@ -993,11 +995,11 @@ kpm_status kpm_solve_begin(kpm_ham *h, int32_t M, int32_t R, int32_t vec, uint64
     kpm_status e = upload(s->tab_dev, &s->inst, sizeof(Inst), st);
     s->wide = p.wide;
     if (p.mode == MODE_SMALL) {
-        // the whole recursion runs now; its dots are final
+        // the whole recursion runs now; its partials are reduced by finish
         if (e == KPM_OK) e = launch_small(h->prec, h->opk, s->tab_dev, 1, 2 * (size_t)p.nel * 16, st);
         s->next = p.K;
         s->written = p.K + 1;
-        s->reduced = p.K + 1;
+        s->reduced = 0;
         if (e != KPM_OK) {
             delete s;
             return e;
@@ -1374,8 +1376,12 @@ kpm_status kpm_moments_batched(kpm_ham *const *h, int32_t count, const int32_t *
     uint32_t *map_dev = (uint32_t *)(base + L.map_off);
     kpm_status e = upload(tab_dev, tab.data(), tab.size() * sizeof(Inst), st);
     if (e == KPM_OK && !map.empty()) e = upload(map_dev, map.data(), map.size() * 4, st);
-    for (const BatchGroup &g : L.small)
+    for (const BatchGroup &g : L.small) {
+        int32_t kmax = 0;
+        for (uint32_t t = g.first; t < g.first + g.count; ++t) kmax = std::max(kmax, L.plans[L.order[t]].K);
         if (e == KPM_OK) e = launch_small(L.prec, g.opk, tab_dev + g.first, g.count, g.lds, st);
+        if (e == KPM_OK) e = launch_reduce(tab_dev + g.first, (int32_t)g.count, -1, kmax + 1, st);
+    }
     for (const BatchWave &w : L.waves) {
         for (const BatchGroup &g : w.groups)
             if (e == KPM_OK) e = launch_init(L.prec, g.wide, tab_dev + g.first, map_dev + g.map_off, g.blocks, st);
