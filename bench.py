@@ -40,6 +40,13 @@ WORKLOAD_TEXT = {
 
 
 CONFIG3_KERNEL = "k_step_march<float, OP_SPIN3> (multi-instance)"
+TB_KERNEL = {2: "k_step_tb<float> (two steps per launch)", 3: "k_step_tb3<float> (three steps per launch)"}
+
+
+def kpm_default_tblock():
+    """The library's default KPM_LAUNCH_TBLOCK (passes of 2 or 3 steps)."""
+    import paper_1105_5481_amd as kpm
+    return kpm.get_launch()["tblock"]
 FP64_MFMA_PEAK_TFLOPS = 78.6
 
 
@@ -248,7 +255,7 @@ def algorithmic_bytes_per_step(N, R, cplx, esz, has_diag, bonds_per_site):
 def kernel_source_digest():
     import hashlib
     h = hashlib.sha256()
-    for f in ("kpm_kernels.hpp", "kpm_device.hpp"):
+    for f in ("kpm_kernels.hpp", "kpm_device.hpp", "kpm_tblock.hpp"):
         h.update(open(os.path.join(ROOT, "paper_1105_5481_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -474,7 +481,7 @@ def main():
         import paper_1105_5481_amd.workloads as wl
         cfg = getattr(wl, args.workload)()
         kern = {"config2": "k_step_march<float, OP_SPIN3>", "config3": CONFIG3_KERNEL,
-                "config4": "k_step_tb<float> (two steps per launch)"}[args.workload]
+                "config4": TB_KERNEL[3 if kpm_default_tblock() == 3 else 2]}[args.workload]
         extra = {"config2": "--no-fp64 --no-cpu-baseline --no-serve ", "config4": "--no-fp64 --no-cpu-baseline --no-serve ",
                  "config3": ""}[args.workload]
         cmds = [f"rocprofv3 --pmc {c} --output-format csv -d <dir> -o p -- python3 bench.py --workload "
@@ -597,13 +604,14 @@ def main():
     updates = float(N) * M * R
     value = updates / (dt32 / args.steps)
     tblocked = solve_mode.get(kpm.F32) == 3
-    nrec = K if tblocked else K - 1          # begin runs step 0 except with two steps per launch
+    depth = (3 if kpm.get_launch()["tblock"] == 3 else 2) if tblocked else 1   # recursion steps per launch
+    nrec = K if tblocked else K - 1          # begin runs step 0 except with temporal blocking
     step_us = rec32 * 1e3 / nrec             # per recursion step
     bonds = lat.dim if lat.hop == wl.HOP_SPIN else 0
     mode = "march" if kpm.get_launch()["march"] else "flat"
     kernel_name = "k_step_%s<float, %s>" % (mode, "OP_SPIN3" if bonds else "OP_REAL2")
     if tblocked:
-        kernel_name = "k_step_tb<float> (two steps per launch)"
+        kernel_name = TB_KERNEL[depth]
     bytes_step = algorithmic_bytes_per_step(N, R, cplx, 4, s32[0].b != 0.0 or lat.onsite is not None, bonds)
     achieved = bytes_step / (step_us * 1e-6) / 1e9
     # same start vectors for the c64 / c128 comparison
@@ -620,12 +628,13 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(args.workload, kernel_name),
                      "kernel": kernel_name,
-                     "bytes_per_launch": bytes_step,
-                     "avg_launch_us": step_us},
+                     "bytes_per_launch": bytes_step * depth,
+                     "avg_launch_us": step_us * depth},
     }
     if tblocked:
-        out["roofline"]["note"] = ("two recursion steps per launch: bytes_per_launch and avg_launch_us are per step "
-                                   "(the method's 3 vector streams per step; the kernel moves about 2)")
+        out["roofline"]["note"] = (f"{depth} recursion steps per launch: bytes_per_launch counts the method's 3 vector "
+                                   f"streams for each of them; the kernel itself moves 4 vector streams per launch "
+                                   f"(plus halo re-reads)")
 
     if not args.no_fp64:
         s64 = make_solver(kpm.F64)

@@ -336,11 +336,14 @@ kpm_status kpm_start_vectors(int32_t vec, int32_t complex_layout, uint64_t seed,
  *                                vectors and operators total at most this many MiB (default
  *                                224, so a wave stays in the Infinity Cache); a wave runs all
  *                                its recursion steps before the next starts.  0 = one wave
- *   KPM_LAUNCH_TBLOCK            1 (default): solves on 2D lattices with real hopping (C <= 64
- *                                chunks per site dividing 512, L_x >= 512/C) run two
- *                                recursion steps per pass over the vectors (temporal
- *                                blocking; 4 vector buffers instead of 2, bitwise the same
- *                                vectors); 0: one step per pass.  Batched solves
+ *   KPM_LAUNCH_TBLOCK            solves on 2D lattices with real hopping (C <= 64 chunks per
+ *                                site dividing 512, L_x >= 512/C) take several recursion
+ *                                steps per pass over the vectors (temporal blocking; 4
+ *                                vector buffers instead of 2, bitwise the same vectors):
+ *                                3 (default): three steps per pass where at least three
+ *                                remain (only r_{n+2} and r_{n+3} are written; L_y >= 6),
+ *                                pairs and single steps for the rest; 1: two steps per pass
+ *                                (L_y >= 4); 0: one step per pass.  Batched solves
  *                                (kpm_moments_batched) always take one step per pass
  * The partial sums of the dot products are formed per work item, so the
  * moments do not depend on the grid (MAX_BLOCKS) nor on the batch an instance

@@ -29,7 +29,7 @@ int g_alternate = 1;                    // march: odd segments walk downwards
 int g_small = 1;                        // solves whose two vector blocks fit in LDS run in one workgroup
 int g_streaming = 2;                    // march: 0 cached, 1 non-temporal access of r_{n-1}/r_{n+1}, 2 by size
 int g_wave_mib = 224;                   // batched solves: vectors + operators per wave (MiB), 0 = one wave
-int g_tblock = 1;                       // 2D real lattices: two recursion steps per pass (temporal blocking)
+int g_tblock = 3;                       // 2D real lattices: steps per pass (temporal blocking): 0 one, 1 two, 3 three
 // Up to this much state (vectors + operator) r_{n+1} is stored cached, to be read back as r_n
 // from the 256 MiB Infinity Cache; measured on 64 x 64 x L_z spin lattices (c64, R = 32),
 // cached stores still win at 251 MiB (5.46 vs 5.00 TB/s; 234 MiB: 6.22 vs 5.01).
@@ -503,6 +503,7 @@ struct Plan {
     size_t esz;
     size_t part_bytes, dots_bytes, buf_bytes;
     uint32_t nbuf;    // vector buffers (2, or 4 with temporal blocking)
+    int32_t tbh;      // temporal blocking: x-tile halo (2, or 3 with three-step passes)
     uint64_t state;   // bytes the recursion touches per step (vectors + operator)
 };
 
@@ -541,11 +542,12 @@ bool make_plan(const kpm_ham *h, int32_t M, int32_t R, int32_t vec, Plan &p, boo
         p.tiles = SMALL_WAVES;   // per-wave dot partials
         p.xcd = 0;
     } else if (allow_tb && g_tblock && g_march && h->opk == OP_REAL2 && p.C <= TB_BLOCK / 8 && TB_BLOCK % p.C == 0 &&
-               h->L[0] >= TB_BLOCK / p.C && h->L[1] >= 4) {
-        // two steps per pass: x-tiles of TB_BLOCK/C - 4 owned sites, segments of rows
+               h->L[0] >= TB_BLOCK / p.C && h->L[1] >= 2 * (g_tblock == 3 ? 3 : 2)) {
+        // two (or three) steps per pass: x-tiles of TB_BLOCK/C - 2 tbh owned sites, segments of rows
         p.mode = MODE_TB;
         p.nbuf = 4;
-        const uint32_t Tn = TB_BLOCK / p.C - 4;
+        p.tbh = g_tblock == 3 ? 3 : 2;
+        const uint32_t Tn = TB_BLOCK / p.C - 2 * (uint32_t)p.tbh;
         p.P = (uint32_t)h->L[0];
         p.Lm = (uint32_t)h->L[1];
         p.nct = (p.P + Tn - 1) / Tn;
@@ -643,6 +645,7 @@ void fill_inst(const kpm_ham *h, const Plan &p, int32_t M, int32_t R, int32_t ve
     I.vec = vec;
     I.step0 = 0;
     I.pslots = p.P_slots;
+    I.tbh = p.tbh;
     I.seed = seed;
     I.instance = instance;
     I.norm = (vec == KPM_VEC_UNIT) ? (double)R : (double)h->N * (double)R;
@@ -670,6 +673,20 @@ kpm_status launch_tb(int prec, int wide, int nt, const Inst *tab, uint32_t block
          {k_step_tb<float, true, false>, k_step_tb<float, true, true>}}};
     const tb_fn f = fns[prec == KPM_F64 ? 0 : 1][wide ? 1 : 0][nt ? 1 : 0];
     hipLaunchKernelGGL(f, dim3(blocks), dim3(TB_BLOCK), 0, st, tab, n, phase, prev, cur, out1, out2);
+    return check_launch();
+}
+
+kpm_status launch_tb3(int prec, int wide, int nt, const Inst *tab, uint32_t blocks, int32_t n, const void *prev,
+                      const void *cur, void *out2, void *out3, hipStream_t st)
+{
+    typedef void (*tb3_fn)(const Inst *, int32_t, const void *, const void *, void *, void *);
+    static const tb3_fn fns[2][2][2] = {
+        {{k_step_tb3<double, false, false>, k_step_tb3<double, false, true>},
+         {k_step_tb3<double, true, false>, k_step_tb3<double, true, true>}},
+        {{k_step_tb3<float, false, false>, k_step_tb3<float, false, true>},
+         {k_step_tb3<float, true, false>, k_step_tb3<float, true, true>}}};
+    const tb3_fn f = fns[prec == KPM_F64 ? 0 : 1][wide ? 1 : 0][nt ? 1 : 0];
+    hipLaunchKernelGGL(f, dim3(blocks), dim3(TB_BLOCK), 0, st, tab, n, prev, cur, out2, out3);
     return check_launch();
 }
 
@@ -1059,18 +1076,26 @@ kpm_status kpm_solve_advance(kpm_solve *s, int32_t max_steps, void *stream, int3
     const Inst &I = s->inst;
     kpm_status e = KPM_OK;
     if (I.mode == MODE_TB) {
-        // pairs of steps; a single step for an odd remainder or a budget of one
+        // triples of steps (3-site halos) or pairs; a pair or a single step for
+        // the remainder or a smaller budget
         int32_t done = 0;
         while (done < max_steps && s->next < I.K && e == KPM_OK) {
-            const bool two = (I.K - s->next >= 2) && (max_steps - done >= 2);
-            const int32_t adv = two ? 2 : 1;
+            const int32_t room = std::min(I.K - s->next, max_steps - done);
+            const int32_t adv = (I.tbh == 3 && room >= 3) ? 3 : (room >= 2 ? 2 : 1);
+            const bool two = adv >= 2;
             if (s->written - s->reduced + adv > I.pslots) e = solve_reduce_pending(s, st);
             if (e != KPM_OK) break;
             int f[2], nf = 0;
             for (int q = 0; q < 4; ++q)
                 if (q != s->tb_prev && q != s->tb_cur) f[nf++] = q;
-            e = launch_tb(s->h->prec, s->wide, I.nt, s->tab_dev, I.nb, s->next, two ? 1 : 2, s->tbuf[s->tb_prev],
-                          s->tbuf[s->tb_cur], s->tbuf[f[0]], s->tbuf[f[1]], st);
+            if (adv == 3) {
+                // r_{n+2}, r_{n+3} into the free buffers, which become (prev, cur) as after a pair
+                e = launch_tb3(s->h->prec, s->wide, I.nt, s->tab_dev, I.nb, s->next, s->tbuf[s->tb_prev],
+                               s->tbuf[s->tb_cur], s->tbuf[f[0]], s->tbuf[f[1]], st);
+            } else {
+                e = launch_tb(s->h->prec, s->wide, I.nt, s->tab_dev, I.nb, s->next, two ? 1 : 2,
+                              s->tbuf[s->tb_prev], s->tbuf[s->tb_cur], s->tbuf[f[0]], s->tbuf[f[1]], st);
+            }
             if (two) {
                 s->tb_prev = f[0];
                 s->tb_cur = f[1];
@@ -1930,7 +1955,7 @@ kpm_status kpm_set_launch(int32_t key, int32_t value)
         g_wave_mib = value;
         return KPM_OK;
     case KPM_LAUNCH_TBLOCK:
-        if (value != 0 && value != 1) return KPM_ERR_INVALID_ARG;
+        if (value != 0 && value != 1 && value != 3) return KPM_ERR_INVALID_ARG;
         g_tblock = value;
         return KPM_OK;
     }

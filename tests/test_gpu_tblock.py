@@ -1,7 +1,7 @@
-"""Temporal blocking (two recursion steps per pass) on 2D real lattices: the vectors are bitwise
-those of the one-step recursion, so FP64 moments match the oracle to the usual bar and both
-precisions match the one-step path; odd step counts and odd chunk sizes exercise the single-step
-pass between pairs."""
+"""Temporal blocking (two, or three, recursion steps per pass) on 2D real lattices: the vectors
+are bitwise those of the one-step recursion, so FP64 moments match the oracle to the usual bar and
+both precisions match the one-step path; step counts and chunk sizes that are not multiples of the
+pass depth exercise the pair and single-step passes between deeper ones."""
 import numpy as np
 import pytest
 
@@ -20,7 +20,10 @@ CASES = [  # (Lx, Ly, W, R, prec, M): C = 4, 1, 16, 16 chunks per site -> window
     (200, 30, 1.0, 8, kpm.F64, 1),     # start vectors only
     (200, 30, 1.0, 8, kpm.F64, 2),     # one single step
     (200, 30, 1.0, 8, kpm.F64, 5),     # a pair and a single step
+    (200, 30, 1.0, 8, kpm.F64, 7),     # one triple (three-step passes)
+    (200, 30, 1.0, 8, kpm.F32, 9),     # a triple and a single step
 ]
+DEPTHS = [1, 3]   # KPM_LAUNCH_TBLOCK: two or three steps per pass
 
 
 def _lat(Lx, Ly, W, seed):
@@ -28,13 +31,14 @@ def _lat(Lx, Ly, W, seed):
     return wl.Lattice(dim=2, L=(Lx, Ly, 1), t=1.0, onsite=onsite)
 
 
+@pytest.mark.parametrize("tb", DEPTHS)
 @pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}x{c[1]}-R{c[3]}-{'f64' if c[4] == 0 else 'f32'}-M{c[5]}")
-def test_tblock_matches_oracle_and_one_step(case):
+def test_tblock_matches_oracle_and_one_step(case, tb):
     Lx, Ly, W, R, prec, M = case
     op = _lat(Lx, Ly, W, Lx + Ly)
     lo, hi = gu.oracle_bounds(op)
     a, b = oracle.scale_from_bounds(lo, hi, 0.01)
-    with kpm.launch_settings(small=0, tblock=1):
+    with kpm.launch_settings(small=0, tblock=tb):
         tb = gu.gpu_moments(op, a, b, prec, M, R, wl.VEC_RADEMACHER, seed=5)
     with kpm.launch_settings(small=0, tblock=0):
         one = gu.gpu_moments(op, a, b, prec, M, R, wl.VEC_RADEMACHER, seed=5)
@@ -48,15 +52,17 @@ def test_tblock_matches_oracle_and_one_step(case):
         assert np.abs(tb - one).max() <= 1e-12
 
 
-@pytest.mark.parametrize("chunks", [[1, 1, 3, 2, 5, 100], [3, 3, 3, 100], [2, 100]])
-def test_tblock_chunked_advance(chunks):
-    """Single steps between pairs (odd chunks) keep the buffers and dots consistent."""
+@pytest.mark.parametrize("tb", DEPTHS)
+@pytest.mark.parametrize("chunks", [[1, 1, 3, 2, 5, 100], [3, 3, 3, 100], [2, 100], [4, 1, 7, 100]])
+def test_tblock_chunked_advance(chunks, tb):
+    """Passes of every depth between the others (chunk sizes not multiples of the depth) keep the
+    buffers and dots consistent."""
     import torch
     op = _lat(300, 40, 1.0, 9)
     lo, hi = gu.oracle_bounds(op)
     a, b = oracle.scale_from_bounds(lo, hi, 0.01)
     M, R = 41, 8
-    with kpm.launch_settings(small=0, tblock=1):
+    with kpm.launch_settings(small=0, tblock=tb):
         h = kpm.Hamiltonian(op, a, b, kpm.F64)
         s = kpm.Solve(h, M, R, wl.VEC_RADEMACHER, 3, 0)
         for c in chunks:
@@ -70,12 +76,13 @@ def test_tblock_chunked_advance(chunks):
     gu.assert_fp64(mu, ref, f"chunks {chunks}")
 
 
-def test_tblock_in_a_dynamic_batch():
+@pytest.mark.parametrize("tb", DEPTHS)
+def test_tblock_in_a_dynamic_batch(tb):
     """A temporally blocked solve advanced inside a dynamic batch beside a one-step solve."""
     op1 = _lat(300, 40, 1.0, 11)
     op2 = wl.spin_cubic_lattice(14, seed=12)
     outs = []
-    with kpm.launch_settings(small=0, tblock=1):
+    with kpm.launch_settings(small=0, tblock=tb):
         hs, ss = [], []
         for op in (op1, op2):
             lo, hi = gu.oracle_bounds(op)
@@ -97,3 +104,16 @@ def test_tblock_in_a_dynamic_batch():
         ref = gu.oracle_moments(op, h.a, h.b, 50, 4, wl.VEC_PHASE, 7, 1)
         gu.assert_fp64(mu, ref, "batched")
         h.free()
+
+
+@pytest.mark.parametrize("tb", DEPTHS)
+def test_tblock_mode_is_used(tb):
+    """The solves above do run temporally blocked (plan mode 3), at either depth."""
+    op = _lat(300, 40, 1.0, 13)
+    with kpm.launch_settings(small=0, tblock=tb):
+        h = kpm.Hamiltonian(op, 4.2, 0.0, kpm.F64)
+        s = kpm.Solve(h, 20, 8, wl.VEC_RADEMACHER, 1, 0)
+        mode = kpm.lib().kpm_solve_mode(s._s)
+        s.close()
+        h.free()
+    assert mode == 3

@@ -77,6 +77,7 @@ def test_argument_validation_without_device(L):
     assert L.kpm_set_launch(3, 0) == 1
     assert L.kpm_set_launch(4, 4) == 1
     assert L.kpm_set_launch(5, 2) == 1
+    assert L.kpm_set_launch(9, 2) == 1          # passes of 1, 2 or 3 steps only (0, 1, 3)
     assert L.kpm_set_launch(99, 1) == 1
     d = kpm.HamDesc()
     d.kind = 3
