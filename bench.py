@@ -40,7 +40,17 @@ WORKLOAD_TEXT = {
 
 
 CONFIG3_KERNEL = "k_step_march<float, OP_SPIN3> (multi-instance)"
-TB_KERNEL = {2: "k_step_tb<float> (two steps per launch)", 3: "k_step_tb3<float> (three steps per launch)"}
+TB_KERNEL = {2: "k_step_tb<float> (two steps per launch)", 3: "k_step_tbd<float, 3> (three steps per launch)",
+             4: "k_step_tbd<float, 4> (four steps per launch)", 5: "k_step_tbd<float, 5> (five steps per launch)",
+             6: "k_step_tbd<float, 6> (six steps per launch)"}
+
+
+def tb_depth(tblock, prec):
+    """Steps of the deepest pass of a temporally blocked solve for a KPM_LAUNCH_TBLOCK value (the
+    library's rule: -1 by precision, FP32 4 and FP64 3; 1 pairs)."""
+    if tblock < 0:
+        return 3 if prec == 0 else 4
+    return tblock if tblock >= 3 else 2
 
 
 def kpm_default_tblock():
@@ -481,7 +491,7 @@ def main():
         import paper_1105_5481_amd.workloads as wl
         cfg = getattr(wl, args.workload)()
         kern = {"config2": "k_step_march<float, OP_SPIN3>", "config3": CONFIG3_KERNEL,
-                "config4": TB_KERNEL[3 if kpm_default_tblock() == 3 else 2]}[args.workload]
+                "config4": TB_KERNEL[tb_depth(kpm_default_tblock(), 1)]}[args.workload]
         extra = {"config2": "--no-fp64 --no-cpu-baseline --no-serve ", "config4": "--no-fp64 --no-cpu-baseline --no-serve ",
                  "config3": ""}[args.workload]
         cmds = [f"rocprofv3 --pmc {c} --output-format csv -d <dir> -o p -- python3 bench.py --workload "
@@ -604,7 +614,7 @@ def main():
     updates = float(N) * M * R
     value = updates / (dt32 / args.steps)
     tblocked = solve_mode.get(kpm.F32) == 3
-    depth = (3 if kpm.get_launch()["tblock"] == 3 else 2) if tblocked else 1   # recursion steps per launch
+    depth = tb_depth(kpm.get_launch()["tblock"], kpm.F32) if tblocked else 1   # recursion steps per launch
     nrec = K if tblocked else K - 1          # begin runs step 0 except with temporal blocking
     step_us = rec32 * 1e3 / nrec             # per recursion step
     bonds = lat.dim if lat.hop == wl.HOP_SPIN else 0

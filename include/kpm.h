@@ -340,11 +340,13 @@ kpm_status kpm_start_vectors(int32_t vec, int32_t complex_layout, uint64_t seed,
  *                                site dividing 512, L_x >= 512/C) take several recursion
  *                                steps per pass over the vectors (temporal blocking; 4
  *                                vector buffers instead of 2, bitwise the same vectors):
- *                                3 (default): three steps per pass where at least three
- *                                remain (only r_{n+2} and r_{n+3} are written; L_y >= 6),
- *                                pairs and single steps for the rest; 1: two steps per pass
- *                                (L_y >= 4); 0: one step per pass.  Batched solves
- *                                (kpm_moments_batched) always take one step per pass
+ *                                D = 3 .. 6: D steps per pass where at least D remain (only
+ *                                r_{n+D-1} and r_{n+D} are written; x-tiles with D-site
+ *                                halos, L_y >= 2D), shorter passes for the rest; -1
+ *                                (default): D = 4 for FP32 and 3 for FP64 solves; 1: two
+ *                                steps per pass (L_y >= 4); 0: one step per pass.
+ *                                Batched solves (kpm_moments_batched) always take one step
+ *                                per pass
  * The partial sums of the dot products are formed per work item, so the
  * moments do not depend on the grid (MAX_BLOCKS) nor on the batch an instance
  * runs in; the other keys change the work items and with them the order in

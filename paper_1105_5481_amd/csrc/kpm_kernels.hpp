@@ -69,7 +69,7 @@ struct Inst {
     int32_t M, K, R, vec;
     int32_t step0;     // recursion step n = step0 + (launch offset k)
     int32_t pslots;    // ring slots of partials
-    int32_t tbh;       // temporal blocking: halo sites each side of an x-tile (2, or 3 for three-step passes)
+    int32_t tbh;       // temporal blocking: halo sites each side of an x-tile (= steps of the deepest pass)
     int32_t red_lo, red_n;  // dots indices [red_lo, red_lo + red_n) to reduce (k_reduce_ranges)
     uint64_t seed, instance;
     double norm;       // N R (random kinds) or R (unit vectors)

@@ -29,7 +29,8 @@ int g_alternate = 1;                    // march: odd segments walk downwards
 int g_small = 1;                        // solves whose two vector blocks fit in LDS run in one workgroup
 int g_streaming = 2;                    // march: 0 cached, 1 non-temporal access of r_{n-1}/r_{n+1}, 2 by size
 int g_wave_mib = 224;                   // batched solves: vectors + operators per wave (MiB), 0 = one wave
-int g_tblock = 3;                       // 2D real lattices: steps per pass (temporal blocking): 0 one, 1 two, 3 three
+int g_tblock = -1;                      // 2D real lattices: steps per pass (temporal blocking): 0 one, 1 two, 3..6,
+                                        // -1 by precision (FP32 4, FP64 3: four-step FP64 passes need 150 VGPRs)
 // Up to this much state (vectors + operator) r_{n+1} is stored cached, to be read back as r_n
 // from the 256 MiB Infinity Cache; measured on 64 x 64 x L_z spin lattices (c64, R = 32),
 // cached stores still win at 251 MiB (5.46 vs 5.00 TB/s; 234 MiB: 6.22 vs 5.01).
@@ -503,9 +504,16 @@ struct Plan {
     size_t esz;
     size_t part_bytes, dots_bytes, buf_bytes;
     uint32_t nbuf;    // vector buffers (2, or 4 with temporal blocking)
-    int32_t tbh;      // temporal blocking: x-tile halo (2, or 3 with three-step passes)
+    int32_t tbh;      // temporal blocking: x-tile halo = steps of the deepest pass (2 .. 6)
     uint64_t state;   // bytes the recursion touches per step (vectors + operator)
 };
+
+// Halo (= steps of the deepest pass, 2 for pairs) of a temporally blocked solve.
+int tb_depth(int prec)
+{
+    if (g_tblock < 0) return prec == KPM_F64 ? 3 : 4;
+    return g_tblock >= 3 ? g_tblock : 2;
+}
 
 // Store kind for r_{n+1}: it is read again as r_n by the next step, so keep it
 // cached when everything the recursion touches per step (all instances of a
@@ -542,11 +550,11 @@ bool make_plan(const kpm_ham *h, int32_t M, int32_t R, int32_t vec, Plan &p, boo
         p.tiles = SMALL_WAVES;   // per-wave dot partials
         p.xcd = 0;
     } else if (allow_tb && g_tblock && g_march && h->opk == OP_REAL2 && p.C <= TB_BLOCK / 8 && TB_BLOCK % p.C == 0 &&
-               h->L[0] >= TB_BLOCK / p.C && h->L[1] >= 2 * (g_tblock == 3 ? 3 : 2)) {
-        // two (or three) steps per pass: x-tiles of TB_BLOCK/C - 2 tbh owned sites, segments of rows
+               h->L[0] >= TB_BLOCK / p.C && h->L[1] >= 2 * tb_depth(h->prec)) {
+        // several steps per pass: x-tiles of TB_BLOCK/C - 2 tbh owned sites, segments of rows
         p.mode = MODE_TB;
         p.nbuf = 4;
-        p.tbh = g_tblock == 3 ? 3 : 2;
+        p.tbh = tb_depth(h->prec);
         const uint32_t Tn = TB_BLOCK / p.C - 2 * (uint32_t)p.tbh;
         p.P = (uint32_t)h->L[0];
         p.Lm = (uint32_t)h->L[1];
@@ -676,17 +684,29 @@ kpm_status launch_tb(int prec, int wide, int nt, const Inst *tab, uint32_t block
     return check_launch();
 }
 
-kpm_status launch_tb3(int prec, int wide, int nt, const Inst *tab, uint32_t blocks, int32_t n, const void *prev,
-                      const void *cur, void *out2, void *out3, hipStream_t st)
+// depth-D passes (D = 3 .. 6) of the generic kernel
+typedef void (*tbd_fn)(const Inst *, int32_t, const void *, const void *, void *, void *);
+template <int D>
+tbd_fn tbd_for(int prec, int wide, int nt)
 {
-    typedef void (*tb3_fn)(const Inst *, int32_t, const void *, const void *, void *, void *);
-    static const tb3_fn fns[2][2][2] = {
-        {{k_step_tb3<double, false, false>, k_step_tb3<double, false, true>},
-         {k_step_tb3<double, true, false>, k_step_tb3<double, true, true>}},
-        {{k_step_tb3<float, false, false>, k_step_tb3<float, false, true>},
-         {k_step_tb3<float, true, false>, k_step_tb3<float, true, true>}}};
-    const tb3_fn f = fns[prec == KPM_F64 ? 0 : 1][wide ? 1 : 0][nt ? 1 : 0];
-    hipLaunchKernelGGL(f, dim3(blocks), dim3(TB_BLOCK), 0, st, tab, n, prev, cur, out2, out3);
+    if (prec == KPM_F64)
+        return wide ? (nt ? k_step_tbd<double, true, true, D> : k_step_tbd<double, true, false, D>)
+                    : (nt ? k_step_tbd<double, false, true, D> : k_step_tbd<double, false, false, D>);
+    return wide ? (nt ? k_step_tbd<float, true, true, D> : k_step_tbd<float, true, false, D>)
+                : (nt ? k_step_tbd<float, false, true, D> : k_step_tbd<float, false, false, D>);
+}
+kpm_status launch_tbd(int depth, int prec, int wide, int nt, const Inst *tab, uint32_t blocks, int32_t n,
+                      const void *prev, const void *cur, void *outa, void *outb, hipStream_t st)
+{
+    tbd_fn f = nullptr;
+    switch (depth) {
+    case 3: f = tbd_for<3>(prec, wide, nt); break;
+    case 4: f = tbd_for<4>(prec, wide, nt); break;
+    case 5: f = tbd_for<5>(prec, wide, nt); break;
+    case 6: f = tbd_for<6>(prec, wide, nt); break;
+    default: return KPM_ERR_INVALID_ARG;
+    }
+    hipLaunchKernelGGL(f, dim3(blocks), dim3(TB_BLOCK), 0, st, tab, n, prev, cur, outa, outb);
     return check_launch();
 }
 
@@ -1076,21 +1096,21 @@ kpm_status kpm_solve_advance(kpm_solve *s, int32_t max_steps, void *stream, int3
     const Inst &I = s->inst;
     kpm_status e = KPM_OK;
     if (I.mode == MODE_TB) {
-        // triples of steps (3-site halos) or pairs; a pair or a single step for
-        // the remainder or a smaller budget
+        // passes of tbh steps (tbh >= 3: halos of tbh sites) or pairs; shorter
+        // passes for the remainder or a smaller budget
         int32_t done = 0;
         while (done < max_steps && s->next < I.K && e == KPM_OK) {
             const int32_t room = std::min(I.K - s->next, max_steps - done);
-            const int32_t adv = (I.tbh == 3 && room >= 3) ? 3 : (room >= 2 ? 2 : 1);
+            const int32_t adv = (I.tbh >= 3 && room >= 3) ? std::min(room, I.tbh) : (room >= 2 ? 2 : 1);
             const bool two = adv >= 2;
             if (s->written - s->reduced + adv > I.pslots) e = solve_reduce_pending(s, st);
             if (e != KPM_OK) break;
             int f[2], nf = 0;
             for (int q = 0; q < 4; ++q)
                 if (q != s->tb_prev && q != s->tb_cur) f[nf++] = q;
-            if (adv == 3) {
-                // r_{n+2}, r_{n+3} into the free buffers, which become (prev, cur) as after a pair
-                e = launch_tb3(s->h->prec, s->wide, I.nt, s->tab_dev, I.nb, s->next, s->tbuf[s->tb_prev],
+            if (adv >= 3) {
+                // r_{n+adv-1}, r_{n+adv} into the free buffers, which become (prev, cur) as after a pair
+                e = launch_tbd(adv, s->h->prec, s->wide, I.nt, s->tab_dev, I.nb, s->next, s->tbuf[s->tb_prev],
                                s->tbuf[s->tb_cur], s->tbuf[f[0]], s->tbuf[f[1]], st);
             } else {
                 e = launch_tb(s->h->prec, s->wide, I.nt, s->tab_dev, I.nb, s->next, two ? 1 : 2,
@@ -1955,7 +1975,7 @@ kpm_status kpm_set_launch(int32_t key, int32_t value)
         g_wave_mib = value;
         return KPM_OK;
     case KPM_LAUNCH_TBLOCK:
-        if (value != 0 && value != 1 && value != 3) return KPM_ERR_INVALID_ARG;
+        if (value < -1 || value == 2 || value > 6) return KPM_ERR_INVALID_ARG;
         g_tblock = value;
         return KPM_OK;
     }

@@ -5,7 +5,7 @@
 // transfers for 2 steps instead of 6.  A work item is an x-tile of T sites
 // times a segment of rows (the march axis y).  Its block holds a window of
 // W = TB_BLOCK / C sites (T = W - 2h owned plus h halo sites on each side;
-// h = 2, or 3 when the solve also takes three-step passes, k_step_tb3), one
+// h = 2, or the depth D of the solve's deeper passes, k_step_tbd), one
 // thread per 16-byte chunk, and marches along y with rows y-1, y, y+1 of r_n
 // and rows y-2, y-1 of r_{n+1} in registers; in-row neighbours come through
 // LDS.  Row y of r_{n+1} is computed on the window minus its outer sites (the
@@ -130,36 +130,34 @@ __global__ __launch_bounds__(TB_BLOCK) void k_step_tb(const Inst *__restrict__ t
     }
 }
 
-// Three steps per pass (solves whose x-tiles carry a 3-site halo): reads
-// r_{n-1} and r_n and writes only r_{n+2} and r_{n+3}, which are all the next
-// pass needs; r_{n+1} stays on chip (its dots are formed).  4 vector transfers
-// for 3 steps.  Iteration j of an item handles row y = y0 - 2 + j of r_{n+1}
-// (window minus its outer sites), row y - 1 of r_{n+2} (minus two outer sites
-// each side) and row y - 2 of r_{n+3} (owned sites); in-row neighbours of all
-// three come through LDS, rows y-1 .. y+1 of r_n, y-2 .. y of r_{n+1} and
-// y-3 .. y-1 of r_{n+2} sit in registers.  Every value is formed with the
+// Depth-D passes (D = 3 .. 6; solves whose x-tiles carry a halo of h >= D
+// sites): one launch advances D steps.  It reads r_{n-1} and r_n and writes
+// only r_{n+D-1} and r_{n+D}, all the next pass needs; r_{n+1} .. r_{n+D-2}
+// exist only on chip, where their dots are formed: 4 vector transfers for D
+// steps.  Level k = 1..D computes r_{n+k}; at iteration j (row
+// y = y0 - (D-1) + j) level k handles row y - (k-1) on the sites at least k
+// from the window edge (level D: the owned sites), from level k-1 at rows
+// y - k .. y - k + 2 (level 0 = r_n, rows y - 1 .. y + 1) and level k-2 at
+// row y - (k-1) (r_{n-1} for level 1).  In-row neighbours come through LDS,
+// every level's row double-buffered so that one block barrier per row
+// suffices; rows in registers otherwise.  Every value is formed with the
 // one-step kernel's expression, so the vectors are bitwise those of one-step
 // passes.
-template <typename S, bool WIDE, bool NT>
-__global__ __launch_bounds__(TB_BLOCK) void k_step_tb3(const Inst *__restrict__ tab, int32_t n, const void *prev,
-                                                       const void *cur, void *out2, void *out3)
+template <typename S, bool WIDE, bool NT, int D>
+__global__ __launch_bounds__(TB_BLOCK) void k_step_tbd(const Inst *__restrict__ tab, int32_t n, const void *prev,
+                                                       const void *cur, void *outa, void *outb)
 {
     typedef typename V16<S>::T T;
     typedef Mem<S, WIDE> G;
-    __shared__ T rn_s[TB_BLOCK];
-    __shared__ T r1_s[2][TB_BLOCK];
-    __shared__ T r2_s[2][TB_BLOCK];
+    __shared__ T lv_s[D][2][TB_BLOCK];   // level k's row of the iteration, double-buffered (k < D)
     const Inst I = tab[0];
     const uint32_t C = I.C, Lx = I.P, Ly = I.Lm;
-    const uint32_t Wn = TB_BLOCK / C, Tn = Wn - 6;
+    const uint32_t h = (uint32_t)I.tbh, Wn = TB_BLOCK / C, Tn = Wn - 2 * h;   // h >= D
     const uint32_t tid = threadIdx.x, s = tid / C, c = tid - s * C;
     const bool hd = I.has_diag;
     const S hop = G::lds(I.hop, 0);
     const bool first = (n == 0);
     const T zero = (T)(S)0;
-    double *part1 = I.partial + (size_t)((n + 1) % I.pslots) * I.tiles * 4;
-    double *part2 = I.partial + (size_t)((n + 2) % I.pslots) * I.tiles * 4;
-    double *part3 = I.partial + (size_t)((n + 3) % I.pslots) * I.tiles * 4;
     const ItemRange ir = item_range(I, I.nct, I.nseg);
     for (uint32_t it = ir.first; it < ir.count; it += ir.stride) {
         const uint32_t sl = it / ir.nu;
@@ -167,79 +165,88 @@ __global__ __launch_bounds__(TB_BLOCK) void k_step_tb3(const Inst *__restrict__ 
         const uint32_t tx = ir.ub + (it - sl * ir.nu);
         const uint32_t x0 = tx * Tn;
         const uint32_t xend = min(x0 + Tn, Lx);
-        const uint32_t x = (x0 + Lx - 3 + s) % Lx;
-        const bool own = s >= 3 && s < Wn - 3 && x0 + s - 3 < xend;
-        const bool ring1 = s >= 1 && s + 1 < Wn;
-        const bool ring2 = s >= 2 && s + 2 < Wn;
+        const uint32_t x = (x0 + Lx - h + s) % Lx;
+        const bool own = s >= h && s < Wn - h && x0 + s - h < xend;
         const uint32_t y0 = sg * I.S, y1 = min(y0 + I.S, Ly), ns = y1 - y0;
         const uint32_t t = sg * I.nct + tx;
-        Dots<S> a1, a2, a3;
+        Dots<S> acc[D];
         auto row = [&](int32_t off) { return (y0 + Ly + (uint32_t)off) % Ly; };   // y0 + off, periodic
-        T rnm = G::ld(cur, (x + Lx * row(-3)) * C + c);
-        T rn0 = G::ld(cur, (x + Lx * row(-2)) * C + c);
-        S dm2 = (S)0;
-        S dm = hd ? G::lds(I.diag, x + Lx * row(-3)) : (S)0;
-        S d0 = hd ? G::lds(I.diag, x + Lx * row(-2)) : (S)0;
-        // row y0-1 of r_n (and its diagonal) and row y0-2 of r_{n-1}, one row ahead
-        T rnp_n = G::ld(cur, (x + Lx * row(-1)) * C + c);
-        S dp_n = hd ? G::lds(I.diag, x + Lx * row(-1)) : (S)0;
-        T pv_n = (ring1 && !first) ? G::template ld_s<NT>(prev, (x + Lx * row(-2)) * C + c) : zero;
-        T r1m2 = zero, r1m1 = zero, r2m2 = zero, r2m1 = zero;
-        for (uint32_t j = 0; j <= ns + 3; ++j) {
+        // level 0 (r_n): rows y-1, y, y+1 of the current iteration; diagonal d[q] of row y + 1 - q
+        T rnm = G::ld(cur, (x + Lx * row(-D)) * C + c);
+        T rn0 = G::ld(cur, (x + Lx * row(1 - D)) * C + c);
+        S d[D + 2];
+#pragma unroll
+        for (int q = 0; q < D + 2; ++q) d[q] = (S)0;
+        if (hd) {
+            d[2] = G::lds(I.diag, x + Lx * row(-D));
+            d[1] = G::lds(I.diag, x + Lx * row(1 - D));
+        }
+        T rnp_n = G::ld(cur, (x + Lx * row(2 - D)) * C + c);
+        S dp_n = hd ? G::lds(I.diag, x + Lx * row(2 - D)) : (S)0;
+        T pv_n = (!first && s >= 1 && s + 1 < Wn) ? G::template ld_s<NT>(prev, (x + Lx * row(1 - D)) * C + c) : zero;
+        T m2[D], m1[D];   // level k at rows (its current row) - 2 and - 1, k = 1 .. D-1
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            m2[k] = zero;
+            m1[k] = zero;
+        }
+        const uint32_t iters = ns + 2 * (D - 1);
+        for (uint32_t j = 0; j < iters; ++j) {
             const T rnp = rnp_n;
-            const S dp = dp_n;
             const T pv = pv_n;
-            if (j <= ns + 2) {   // rows the next iteration needs
-                rnp_n = G::ld(cur, (x + Lx * row((int32_t)j)) * C + c);
-                dp_n = hd ? G::lds(I.diag, x + Lx * row((int32_t)j)) : (S)0;
-                if (ring1 && !first) pv_n = G::template ld_s<NT>(prev, (x + Lx * row((int32_t)j - 1)) * C + c);
+            d[0] = dp_n;
+            if (j + 1 < iters) {   // rows the next iteration needs
+                rnp_n = G::ld(cur, (x + Lx * row((int32_t)j + 3 - D)) * C + c);
+                dp_n = hd ? G::lds(I.diag, x + Lx * row((int32_t)j + 3 - D)) : (S)0;
+                if (!first && s >= 1 && s + 1 < Wn)
+                    pv_n = G::template ld_s<NT>(prev, (x + Lx * row((int32_t)j + 2 - D)) * C + c);
             }
-            // r_{n+1}, row y
-            rn_s[tid] = rn0;
+            const uint32_t b = j & 1u, bp = b ^ 1u;
+            lv_s[0][b][tid] = rn0;
             __syncthreads();
-            T r1 = zero;
-            if (ring1) {
-                const T nb[4] = {rn_s[tid - C], rn_s[tid + C], rnm, rnp};
-                r1 = apply_real<S, 4>(hd, d0, hop, rn0, nb);
-                if (!first) r1 = (S)2 * r1 - pv;
+            T cur_k[D + 1];
+            cur_k[0] = rnp;
+#pragma unroll
+            for (int k = 1; k <= D; ++k) {
+                T v = zero;
+                const bool ring = (k < D) ? (s >= (uint32_t)k && s + k < Wn) : own;
+                if (ring && j >= 2u * (uint32_t)(k - 1)) {
+                    if (k == 1) {
+                        const T nb[4] = {lv_s[0][b][tid - C], lv_s[0][b][tid + C], rnm, rnp};
+                        v = apply_real<S, 4>(hd, d[1], hop, rn0, nb);
+                        if (!first) v = (S)2 * v - pv;
+                    } else {
+                        const T lo = (k == 2) ? rnm : m2[k - 2 > 0 ? k - 2 : 0];
+                        const T nb[4] = {lv_s[k - 1][bp][tid - C], lv_s[k - 1][bp][tid + C], m2[k - 1], cur_k[k - 1]};
+                        v = apply_real<S, 4>(hd, d[k], hop, m1[k - 1], nb);
+                        v = (S)2 * v - lo;
+                    }
+                }
+                cur_k[k] = v;
+                // stores and dots on the owned rows [y0, y1): level k is at row offset j - D - k + 2
+                const int32_t ro = (int32_t)j - D - k + 2;
+                if (own && ro >= 0 && ro < (int32_t)ns) {
+                    if (k == D - 1) G::template st_s<NT>(outa, (x + Lx * row(ro)) * C + c, v);
+                    if (k == D) G::template st_s<NT>(outb, (x + Lx * row(ro)) * C + c, v);
+                    acc[k - 1].add(v, k == 1 ? rn0 : m1[k - 1]);
+                }
+                if (k < D) lv_s[k][b][tid] = v;
             }
-            if (own && j >= 2 && j <= ns + 1) a1.add(r1, rn0);
-            r1_s[j & 1][tid] = r1;
-            __syncthreads();
-            // r_{n+2}, row y - 1
-            T r2 = zero;
-            if (j >= 2 && ring2) {
-                const T nb[4] = {r1_s[(j - 1) & 1][tid - C], r1_s[(j - 1) & 1][tid + C], r1m2, r1};
-                r2 = apply_real<S, 4>(hd, dm, hop, r1m1, nb);
-                r2 = (S)2 * r2 - rnm;
+#pragma unroll
+            for (int k = 1; k < D; ++k) {
+                m2[k] = m1[k];
+                m1[k] = cur_k[k];
             }
-            if (own && j >= 3 && j <= ns + 2) {
-                G::template st_s<NT>(out2, (x + Lx * row((int32_t)j - 3)) * C + c, r2);
-                a2.add(r2, r1m1);
-            }
-            r2_s[j & 1][tid] = r2;
-            __syncthreads();
-            // r_{n+3}, row y - 2
-            if (own && j >= 4) {
-                const T nb[4] = {r2_s[(j - 1) & 1][tid - C], r2_s[(j - 1) & 1][tid + C], r2m2, r2};
-                T r3 = apply_real<S, 4>(hd, dm2, hop, r2m1, nb);
-                r3 = (S)2 * r3 - r1m2;
-                G::template st_s<NT>(out3, (x + Lx * row((int32_t)j - 4)) * C + c, r3);
-                a3.add(r3, r2m1);
-            }
-            r2m2 = r2m1;
-            r2m1 = r2;
-            r1m2 = r1m1;
-            r1m1 = r1;
             rnm = rn0;
             rn0 = rnp;
-            dm2 = dm;
-            dm = d0;
-            d0 = dp;
+#pragma unroll
+            for (int q = D + 1; q > 0; --q) d[q] = d[q - 1];
         }
-        block_reduce_store<Dots<S>::DD, TB_BLOCK>(a1.s0, a1.c0, a1.s1, a1.c1, part1 + (size_t)t * 4);
-        block_reduce_store<Dots<S>::DD, TB_BLOCK>(a2.s0, a2.c0, a2.s1, a2.c1, part2 + (size_t)t * 4);
-        block_reduce_store<Dots<S>::DD, TB_BLOCK>(a3.s0, a3.c0, a3.s1, a3.c1, part3 + (size_t)t * 4);
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+            block_reduce_store<Dots<S>::DD, TB_BLOCK>(acc[k].s0, acc[k].c0, acc[k].s1, acc[k].c1,
+                                                      I.partial + (size_t)((n + 1 + k) % I.pslots) * I.tiles * 4 +
+                                                          (size_t)t * 4);
     }
 }
 

@@ -2,7 +2,7 @@
 
 The recursion kernels take their work decomposition from the library's launch keys (march
 segments, XCD split, segment direction, store kind, block cap, chunks per thread, batch waves,
-two or three steps per pass).
+steps per pass).
 The best values depend on the operator class, the lattice shape, R and the precision, so this
 module times candidates on the caller's own operators and keeps the fastest.
 
@@ -39,7 +39,7 @@ CANDIDATES: Dict[str, List[int]] = {
     "max_blocks": [512, 1024, 2048, 4096, 8192],
     "elems_per_thread": [1, 2, 4],
     "wave_mib": [0, 128, 192, 224, 256],
-    "tblock": [0, 1, 3],
+    "tblock": [-1, 0, 1, 3, 4, 5],
 }
 LATTICE_KEYS = ["march_items", "xcd_split", "alternate", "streaming", "max_blocks", "tblock"]
 FLAT_KEYS = ["elems_per_thread", "max_blocks"]

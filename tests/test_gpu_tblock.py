@@ -23,7 +23,7 @@ CASES = [  # (Lx, Ly, W, R, prec, M): C = 4, 1, 16, 16 chunks per site -> window
     (200, 30, 1.0, 8, kpm.F64, 7),     # one triple (three-step passes)
     (200, 30, 1.0, 8, kpm.F32, 9),     # a triple and a single step
 ]
-DEPTHS = [1, 3]   # KPM_LAUNCH_TBLOCK: two or three steps per pass
+DEPTHS = [1, 3, 4, 5, 6]   # KPM_LAUNCH_TBLOCK: steps per pass (1 means two)
 
 
 def _lat(Lx, Ly, W, seed):
