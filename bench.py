@@ -40,21 +40,23 @@ WORKLOAD_TEXT = {
 
 
 CONFIG3_KERNEL = "k_step_march<float, OP_SPIN3> (multi-instance)"
-TB_KERNEL = {2: "k_step_tb<float> (two steps per launch)", 3: "k_step_tbd<float, 3> (three steps per launch)",
-             4: "k_step_tbd<float, 4> (four steps per launch)", 5: "k_step_tbd<float, 5> (five steps per launch)",
-             6: "k_step_tbd<float, 6> (six steps per launch)"}
+TB_KERNEL = {d: "k_step_tbd<float, OP_REAL2, %d> (%d step%s per launch)" % (d, d, "s" if d > 1 else "")
+             for d in range(1, 7)}
 
 
-def tb_depth(tblock, prec):
+def tb_depth(tblock, prec, C=16):
     """Steps of the deepest pass of a temporally blocked solve for a KPM_LAUNCH_TBLOCK value (the
-    library's rule: -1 by precision, FP32 4 and FP64 3; 1 pairs)."""
+    library's rule: -1 by precision, FP32 4 and FP64 3; 1 pairs; at most a quarter of the window
+    of 512 / C sites, C = 16-byte chunks per site)."""
     if tblock < 0:
-        return 3 if prec == 0 else 4
-    return tblock if tblock >= 3 else 2
+        d = 3 if prec == 0 else 4
+    else:
+        d = tblock if tblock >= 3 else 2
+    return min(d, 512 // C // 4)
 
 
 def kpm_default_tblock():
-    """The library's default KPM_LAUNCH_TBLOCK (passes of 2 or 3 steps)."""
+    """The library's default KPM_LAUNCH_TBLOCK."""
     import paper_1105_5481_amd as kpm
     return kpm.get_launch()["tblock"]
 FP64_MFMA_PEAK_TFLOPS = 78.6
@@ -471,7 +473,7 @@ def main():
     ap.add_argument("--alternate", type=int, default=-1)
     ap.add_argument("--streaming", type=int, default=-1)
     ap.add_argument("--wave-mib", type=int, default=-1, help="batched solves: MiB of state per wave, 0 = one wave")
-    ap.add_argument("--tblock", type=int, default=-1, help="2D real lattices: 1 two steps per pass, 0 one step")
+    ap.add_argument("--tblock", type=int, default=-1, help="2D lattices: steps per pass, 1 two, 3..6, 0 one step")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain 1 GiB device copy three times (counter calibration under rocprofv3)")
     ap.add_argument("--pmc-summary", metavar="DIR",
@@ -614,7 +616,8 @@ def main():
     updates = float(N) * M * R
     value = updates / (dt32 / args.steps)
     tblocked = solve_mode.get(kpm.F32) == 3
-    depth = tb_depth(kpm.get_launch()["tblock"], kpm.F32) if tblocked else 1   # recursion steps per launch
+    chunks = -(-R * (2 if cplx else 1) // 4)  # 16-byte chunks per site (FP32)
+    depth = tb_depth(kpm.get_launch()["tblock"], kpm.F32, chunks) if tblocked else 1   # recursion steps per launch
     nrec = K if tblocked else K - 1          # begin runs step 0 except with temporal blocking
     step_us = rec32 * 1e3 / nrec             # per recursion step
     bonds = lat.dim if lat.hop == wl.HOP_SPIN else 0

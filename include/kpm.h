@@ -336,7 +336,7 @@ kpm_status kpm_start_vectors(int32_t vec, int32_t complex_layout, uint64_t seed,
  *                                vectors and operators total at most this many MiB (default
  *                                224, so a wave stays in the Infinity Cache); a wave runs all
  *                                its recursion steps before the next starts.  0 = one wave
- *   KPM_LAUNCH_TBLOCK            solves on 2D lattices with real hopping (C <= 64 chunks per
+ *   KPM_LAUNCH_TBLOCK            solves on 2D lattices (real or spin hopping; C chunks per
  *                                site dividing 512, L_x >= 512/C) take several recursion
  *                                steps per pass over the vectors (temporal blocking; 4
  *                                vector buffers instead of 2, bitwise the same vectors):
@@ -344,9 +344,11 @@ kpm_status kpm_start_vectors(int32_t vec, int32_t complex_layout, uint64_t seed,
  *                                r_{n+D-1} and r_{n+D} are written; x-tiles with D-site
  *                                halos, L_y >= 2D), shorter passes for the rest; -1
  *                                (default): D = 4 for FP32 and 3 for FP64 solves; 1: two
- *                                steps per pass (L_y >= 4); 0: one step per pass.
- *                                Batched solves (kpm_moments_batched) always take one step
- *                                per pass
+ *                                steps per pass (L_y >= 4); 0: one step per pass.  D is
+ *                                capped at 128/C (a quarter of the 512/C-site window);
+ *                                below 2 the solve takes one step per pass.  Batched
+ *                                solves (kpm_moments_batched) always take one step per
+ *                                pass
  * The partial sums of the dot products are formed per work item, so the
  * moments do not depend on the grid (MAX_BLOCKS) nor on the batch an instance
  * runs in; the other keys change the work items and with them the order in

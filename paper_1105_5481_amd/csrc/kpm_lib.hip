@@ -29,8 +29,8 @@ int g_alternate = 1;                    // march: odd segments walk downwards
 int g_small = 1;                        // solves whose two vector blocks fit in LDS run in one workgroup
 int g_streaming = 2;                    // march: 0 cached, 1 non-temporal access of r_{n-1}/r_{n+1}, 2 by size
 int g_wave_mib = 224;                   // batched solves: vectors + operators per wave (MiB), 0 = one wave
-int g_tblock = -1;                      // 2D real lattices: steps per pass (temporal blocking): 0 one, 1 two, 3..6,
-                                        // -1 by precision (FP32 4, FP64 3: four-step FP64 passes need 150 VGPRs)
+int g_tblock = -1;                      // 2D lattices: steps per pass (temporal blocking): 0 one, 1 two, 3..6,
+                                        // -1 by precision and hopping (tb_depth)
 // Up to this much state (vectors + operator) r_{n+1} is stored cached, to be read back as r_n
 // from the 256 MiB Infinity Cache; measured on 64 x 64 x L_z spin lattices (c64, R = 32),
 // cached stores still win at 251 MiB (5.46 vs 5.00 TB/s; 234 MiB: 6.22 vs 5.01).
@@ -504,15 +504,24 @@ struct Plan {
     size_t esz;
     size_t part_bytes, dots_bytes, buf_bytes;
     uint32_t nbuf;    // vector buffers (2, or 4 with temporal blocking)
-    int32_t tbh;      // temporal blocking: x-tile halo = steps of the deepest pass (2 .. 6)
+    int32_t tbh;      // temporal blocking: x-tile halo = steps of the deepest pass (1 .. 6)
     uint64_t state;   // bytes the recursion touches per step (vectors + operator)
 };
 
 // Halo (= steps of the deepest pass, 2 for pairs) of a temporally blocked solve.
-int tb_depth(int prec)
+// Default (-1) by precision and hopping, measured on 2048^2 lattices: FP32 four steps
+// (real R = 64: 2.45x one step per pass; spin R = 16: 1.46x); FP64 real three (four need
+// 150 VGPRs and run slower); FP64 spin none (three-step passes 0.82x one step).
+int tb_depth(int prec, int opk)
 {
-    if (g_tblock < 0) return prec == KPM_F64 ? 3 : 4;
+    if (g_tblock < 0) return prec == KPM_F64 ? (opk == OP_SPIN2 ? 0 : 3) : 4;
     return g_tblock >= 3 ? g_tblock : 2;
+}
+// The halo actually used with C chunks per site: at most a quarter of the window of
+// TB_BLOCK / C sites, so that at least half of it is owned.
+int tb_halo(int prec, int opk, uint32_t C)
+{
+    return std::min<int>(tb_depth(prec, opk), (int)(TB_BLOCK / C / 4));
 }
 
 // Store kind for r_{n+1}: it is read again as r_n by the next step, so keep it
@@ -549,19 +558,20 @@ bool make_plan(const kpm_ham *h, int32_t M, int32_t R, int32_t vec, Plan &p, boo
         p.mode = MODE_SMALL;
         p.tiles = SMALL_WAVES;   // per-wave dot partials
         p.xcd = 0;
-    } else if (allow_tb && g_tblock && g_march && h->opk == OP_REAL2 && p.C <= TB_BLOCK / 8 && TB_BLOCK % p.C == 0 &&
-               h->L[0] >= TB_BLOCK / p.C && h->L[1] >= 2 * tb_depth(h->prec)) {
+    } else if (allow_tb && g_tblock && g_march && (h->opk == OP_REAL2 || h->opk == OP_SPIN2) &&
+               TB_BLOCK % p.C == 0 && tb_halo(h->prec, h->opk, p.C) >= 2 && h->L[0] >= TB_BLOCK / p.C &&
+               h->L[1] >= 2 * tb_halo(h->prec, h->opk, p.C)) {
         // several steps per pass: x-tiles of TB_BLOCK/C - 2 tbh owned sites, segments of rows
         p.mode = MODE_TB;
         p.nbuf = 4;
-        p.tbh = tb_depth(h->prec);
+        p.tbh = tb_halo(h->prec, h->opk, p.C);
         const uint32_t Tn = TB_BLOCK / p.C - 2 * (uint32_t)p.tbh;
         p.P = (uint32_t)h->L[0];
         p.Lm = (uint32_t)h->L[1];
         p.nct = (p.P + Tn - 1) / Tn;
-        // a block marches with two barriers per row, so more and shorter segments than
-        // the one-step kernels (8x the item target; measured on the 2048^2 lattice:
-        // 4096 items 455 us per step, 512 items 554 us)
+        // more and shorter segments than the one-step kernels (8x the item target;
+        // measured on the 2048^2 lattice with two-step passes: 4096 items 455 us per
+        // step, 512 items 554 us)
         const uint64_t target = 8ull * (uint64_t)g_march_items;
         uint32_t nseg = (uint32_t)((target + p.nct - 1) / p.nct);
         nseg = std::max<uint32_t>(1, std::min<uint32_t>(nseg, std::max<uint32_t>(1, p.Lm / 8)));
@@ -670,40 +680,42 @@ void fill_inst(const kpm_ham *h, const Plan &p, int32_t M, int32_t R, int32_t ve
     I.mu = nullptr;
 }
 
-kpm_status launch_tb(int prec, int wide, int nt, const Inst *tab, uint32_t blocks, int32_t n, int32_t phase,
-                     const void *prev, void *cur, void *out1, void *out2, hipStream_t st)
+kpm_status launch_init_tb(int prec, int wide, const Inst *tab, uint32_t blocks, void *cur, hipStream_t st)
 {
-    typedef void (*tb_fn)(const Inst *, int32_t, int32_t, const void *, void *, void *, void *);
-    static const tb_fn fns[2][2][2] = {
-        {{k_step_tb<double, false, false>, k_step_tb<double, false, true>},
-         {k_step_tb<double, true, false>, k_step_tb<double, true, true>}},
-        {{k_step_tb<float, false, false>, k_step_tb<float, false, true>},
-         {k_step_tb<float, true, false>, k_step_tb<float, true, true>}}};
-    const tb_fn f = fns[prec == KPM_F64 ? 0 : 1][wide ? 1 : 0][nt ? 1 : 0];
-    hipLaunchKernelGGL(f, dim3(blocks), dim3(TB_BLOCK), 0, st, tab, n, phase, prev, cur, out1, out2);
+    typedef void (*fn)(const Inst *, void *);
+    static const fn fns[2][2] = {{k_init_tb<double, false>, k_init_tb<double, true>},
+                                 {k_init_tb<float, false>, k_init_tb<float, true>}};
+    hipLaunchKernelGGL(fns[prec == KPM_F64 ? 0 : 1][wide ? 1 : 0], dim3(blocks), dim3(TB_BLOCK), 0, st, tab, cur);
     return check_launch();
 }
 
-// depth-D passes (D = 3 .. 6) of the generic kernel
+// depth-D passes (D = 1 .. 6) of the temporally blocked kernel, real or spin hopping
 typedef void (*tbd_fn)(const Inst *, int32_t, const void *, const void *, void *, void *);
-template <int D>
-tbd_fn tbd_for(int prec, int wide, int nt)
+template <typename S, int OPK, int D>
+tbd_fn tbd_pick(int wide, int nt)
 {
-    if (prec == KPM_F64)
-        return wide ? (nt ? k_step_tbd<double, true, true, D> : k_step_tbd<double, true, false, D>)
-                    : (nt ? k_step_tbd<double, false, true, D> : k_step_tbd<double, false, false, D>);
-    return wide ? (nt ? k_step_tbd<float, true, true, D> : k_step_tbd<float, true, false, D>)
-                : (nt ? k_step_tbd<float, false, true, D> : k_step_tbd<float, false, false, D>);
+    return wide ? (nt ? k_step_tbd<S, OPK, true, true, D> : k_step_tbd<S, OPK, true, false, D>)
+                : (nt ? k_step_tbd<S, OPK, false, true, D> : k_step_tbd<S, OPK, false, false, D>);
 }
-kpm_status launch_tbd(int depth, int prec, int wide, int nt, const Inst *tab, uint32_t blocks, int32_t n,
+template <int D>
+tbd_fn tbd_for(int prec, int opk, int wide, int nt)
+{
+    if (opk == OP_SPIN2)
+        return prec == KPM_F64 ? tbd_pick<double, OP_SPIN2, D>(wide, nt) : tbd_pick<float, OP_SPIN2, D>(wide, nt);
+    return prec == KPM_F64 ? tbd_pick<double, OP_REAL2, D>(wide, nt) : tbd_pick<float, OP_REAL2, D>(wide, nt);
+}
+kpm_status launch_tbd(int depth, int prec, int opk, int wide, int nt, const Inst *tab, uint32_t blocks, int32_t n,
                       const void *prev, const void *cur, void *outa, void *outb, hipStream_t st)
 {
+    if (opk != OP_REAL2 && opk != OP_SPIN2) return KPM_ERR_INVALID_ARG;
     tbd_fn f = nullptr;
     switch (depth) {
-    case 3: f = tbd_for<3>(prec, wide, nt); break;
-    case 4: f = tbd_for<4>(prec, wide, nt); break;
-    case 5: f = tbd_for<5>(prec, wide, nt); break;
-    case 6: f = tbd_for<6>(prec, wide, nt); break;
+    case 1: f = tbd_for<1>(prec, opk, wide, nt); break;
+    case 2: f = tbd_for<2>(prec, opk, wide, nt); break;
+    case 3: f = tbd_for<3>(prec, opk, wide, nt); break;
+    case 4: f = tbd_for<4>(prec, opk, wide, nt); break;
+    case 5: f = tbd_for<5>(prec, opk, wide, nt); break;
+    case 6: f = tbd_for<6>(prec, opk, wide, nt); break;
     default: return KPM_ERR_INVALID_ARG;
     }
     hipLaunchKernelGGL(f, dim3(blocks), dim3(TB_BLOCK), 0, st, tab, n, prev, cur, outa, outb);
@@ -1050,8 +1062,7 @@ kpm_status kpm_solve_begin(kpm_ham *h, int32_t M, int32_t R, int32_t vec, uint64
         for (int q = 0; q < 4; ++q) s->tbuf[q] = b + (size_t)q * p.buf_bytes;
         s->tb_prev = 0;
         s->tb_cur = 1;
-        if (e == KPM_OK) e = launch_tb(h->prec, p.wide, p.nt, s->tab_dev, p.nb, 0, 0, s->tbuf[0], s->tbuf[1],
-                                       s->tbuf[2], s->tbuf[3], st);
+        if (e == KPM_OK) e = launch_init_tb(h->prec, p.wide, s->tab_dev, p.nb, s->tbuf[1], st);
         s->written = 1;
         s->reduced = 0;
         s->next = 0;
@@ -1096,27 +1107,22 @@ kpm_status kpm_solve_advance(kpm_solve *s, int32_t max_steps, void *stream, int3
     const Inst &I = s->inst;
     kpm_status e = KPM_OK;
     if (I.mode == MODE_TB) {
-        // passes of tbh steps (tbh >= 3: halos of tbh sites) or pairs; shorter
-        // passes for the remainder or a smaller budget
+        // passes of tbh steps (the tiles' halo); a shorter one for the remainder or a
+        // smaller budget
         int32_t done = 0;
         while (done < max_steps && s->next < I.K && e == KPM_OK) {
-            const int32_t room = std::min(I.K - s->next, max_steps - done);
-            const int32_t adv = (I.tbh >= 3 && room >= 3) ? std::min(room, I.tbh) : (room >= 2 ? 2 : 1);
-            const bool two = adv >= 2;
+            const int32_t adv = std::min(std::min(I.K - s->next, max_steps - done), I.tbh);
             if (s->written - s->reduced + adv > I.pslots) e = solve_reduce_pending(s, st);
             if (e != KPM_OK) break;
             int f[2], nf = 0;
             for (int q = 0; q < 4; ++q)
                 if (q != s->tb_prev && q != s->tb_cur) f[nf++] = q;
-            if (adv >= 3) {
-                // r_{n+adv-1}, r_{n+adv} into the free buffers, which become (prev, cur) as after a pair
-                e = launch_tbd(adv, s->h->prec, s->wide, I.nt, s->tab_dev, I.nb, s->next, s->tbuf[s->tb_prev],
-                               s->tbuf[s->tb_cur], s->tbuf[f[0]], s->tbuf[f[1]], st);
-            } else {
-                e = launch_tb(s->h->prec, s->wide, I.nt, s->tab_dev, I.nb, s->next, two ? 1 : 2,
-                              s->tbuf[s->tb_prev], s->tbuf[s->tb_cur], s->tbuf[f[0]], s->tbuf[f[1]], st);
-            }
-            if (two) {
+            // r_{n+adv-1}, r_{n+adv} into the free buffers, which become (prev, cur); a single
+            // step writes r_{n+1} alone
+            e = launch_tbd(adv, s->h->prec, s->h->opk, s->wide, I.nt, s->tab_dev, I.nb, s->next,
+                           s->tbuf[s->tb_prev], s->tbuf[s->tb_cur], s->tbuf[adv >= 2 ? f[0] : f[1]],
+                           s->tbuf[adv >= 2 ? f[1] : f[0]], st);
+            if (adv >= 2) {
                 s->tb_prev = f[0];
                 s->tb_cur = f[1];
             } else {

@@ -1,7 +1,8 @@
-"""Temporal blocking (two, or three, recursion steps per pass) on 2D real lattices: the vectors
-are bitwise those of the one-step recursion, so FP64 moments match the oracle to the usual bar and
-both precisions match the one-step path; step counts and chunk sizes that are not multiples of the
-pass depth exercise the pair and single-step passes between deeper ones."""
+"""Temporal blocking (several recursion steps per pass) on 2D lattices with real or spin hopping:
+the vectors are bitwise those of the one-step recursion, so FP64 moments match the oracle to the
+usual bar and both precisions match the one-step path; step counts and chunk sizes that are not
+multiples of the pass depth exercise the shorter passes between the deepest ones, and wide sites
+(many chunks) the cap of the depth at a quarter of the tile window."""
 import numpy as np
 import pytest
 
@@ -29,6 +30,62 @@ DEPTHS = [1, 3, 4, 5, 6]   # KPM_LAUNCH_TBLOCK: steps per pass (1 means two)
 def _lat(Lx, Ly, W, seed):
     onsite = wl.anderson_onsite(Lx * Ly, W, seed) if W > 0 else None
     return wl.Lattice(dim=2, L=(Lx, Ly, 1), t=1.0, onsite=onsite)
+
+
+def _spin_lat(Lx, Ly, W, seed):
+    onsite = wl.anderson_onsite(Lx * Ly, W, seed) if W > 0 else None
+    theta, phi = wl.spins_uniform(Lx * Ly, seed)
+    return wl.Lattice(dim=2, L=(Lx, Ly, 1), t=1.0, hop=wl.HOP_SPIN, onsite=onsite,
+                      spinor=wl.spinor_of(theta, phi), theta=theta, phi=phi)
+
+
+SPIN_CASES = [  # (Lx, Ly, W, R, prec, M, vector kind, spin hopping): chunks per site C -> depth cap 128 / C
+    (200, 24, 1.0, 4, kpm.F64, 40, wl.VEC_PHASE, True),      # C = 4
+    (96, 20, 0.0, 64, kpm.F32, 31, wl.VEC_PHASE, True),      # C = 32: depth capped at 4
+    (40, 12, 0.5, 128, kpm.F32, 13, wl.VEC_PHASE, True),     # C = 64: depth capped at 2
+    (300, 18, 1.0, 3, kpm.F32, 26, wl.VEC_RADEMACHER, True),  # C = 2: real vectors, complex operator
+    (150, 20, 1.0, 8, kpm.F64, 30, wl.VEC_PHASE, False),     # C = 8: real hopping, complex vectors
+]
+
+
+@pytest.mark.parametrize("tb", DEPTHS)
+@pytest.mark.parametrize("case", SPIN_CASES,
+                         ids=lambda c: f"{'spin' if c[7] else 'real'}{c[0]}x{c[1]}-R{c[3]}-{'f64' if c[4] == 0 else 'f32'}-v{c[6]}")
+def test_tblock_complex_matches_oracle_and_one_step(case, tb):
+    Lx, Ly, W, R, prec, M, vec, spin = case
+    op = (_spin_lat if spin else _lat)(Lx, Ly, W, Lx * Ly + 3)
+    lo, hi = gu.oracle_bounds(op)
+    a, b = oracle.scale_from_bounds(lo, hi, 0.01)
+    with kpm.launch_settings(small=0, tblock=tb):
+        h = kpm.Hamiltonian(op, a, b, prec)
+        s = kpm.Solve(h, 20, R, vec, 1, 0)
+        mode = kpm.lib().kpm_solve_mode(s._s)
+        s.close()
+        h.free()
+        got = gu.gpu_moments(op, a, b, prec, M, R, vec, seed=6)
+    assert mode == 3
+    with kpm.launch_settings(small=0, tblock=0):
+        one = gu.gpu_moments(op, a, b, prec, M, R, vec, seed=6)
+    ref = gu.oracle_moments(op, a, b, M, R, vec, 6)
+    print(f"  tblock vs one-step {np.abs(got - one).max():.2e}, vs oracle {np.abs(got - ref).max():.2e}")
+    if prec == kpm.F64:
+        gu.assert_fp64(got, ref, "temporal blocking")
+        assert np.abs(got - one).max() <= 1e-15
+    else:
+        gu.assert_fp32(got, ref, "temporal blocking")
+        assert np.abs(got - one).max() <= 1e-12
+
+
+def test_tblock_off_when_sites_are_too_wide():
+    """128 chunks per site leave a 4-site window: too narrow for any halo, so one step per pass."""
+    op = _spin_lat(40, 12, 0.0, 5)
+    with kpm.launch_settings(small=0, tblock=4):
+        h = kpm.Hamiltonian(op, 4.5, 0.0, kpm.F32)
+        s = kpm.Solve(h, 20, 256, wl.VEC_PHASE, 1, 0)
+        mode = kpm.lib().kpm_solve_mode(s._s)
+        s.close()
+        h.free()
+    assert mode != 3
 
 
 @pytest.mark.parametrize("tb", DEPTHS)
@@ -117,3 +174,17 @@ def test_tblock_mode_is_used(tb):
         s.close()
         h.free()
     assert mode == 3
+
+
+@pytest.mark.parametrize("prec,spin,expect", [(kpm.F32, True, True), (kpm.F64, True, False),
+                                              (kpm.F32, False, True), (kpm.F64, False, True)])
+def test_tblock_default_by_precision_and_hopping(prec, spin, expect):
+    """The default (-1) blocks FP32 solves and FP64 real hopping, not FP64 spin hopping."""
+    op = (_spin_lat if spin else _lat)(300, 40, 1.0, 17)
+    with kpm.launch_settings(small=0, tblock=-1):
+        h = kpm.Hamiltonian(op, 4.6, 0.0, prec)
+        s = kpm.Solve(h, 20, 8, wl.VEC_PHASE, 1, 0)
+        mode = kpm.lib().kpm_solve_mode(s._s)
+        s.close()
+        h.free()
+    assert (mode == 3) == expect
