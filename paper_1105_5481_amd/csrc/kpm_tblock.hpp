@@ -16,6 +16,9 @@ namespace kpm {
 
 constexpr int TB_BLOCK = 512;
 constexpr int MODE_TB = 3;   // plan mode of solves run by these kernels
+// Passes shallow enough for two blocks per CU in LDS (D <= 4: 16 KiB per level)
+// are held to 128 VGPRs (4 waves per SIMD), so that the second block fits.
+#define TB_WAVES_PER_EU(S, D) ((sizeof(S) == 4 ? (D) <= 4 : (D) <= 3) ? 4 : 1)
 
 // r_0 (and the partials of <r_0|r_0>, slot 0) into `cur` over the solve's work
 // items (the owned sites of each tile and segment).
@@ -64,7 +67,7 @@ __global__ __launch_bounds__(TB_BLOCK) void k_init_tb(const Inst *__restrict__ t
 // one-step kernel's expression, so the vectors are bitwise those of one-step
 // passes.
 template <typename S, int OPK, bool WIDE, bool NT, int D>
-__global__ __launch_bounds__(TB_BLOCK) void k_step_tbd(const Inst *__restrict__ tab, int32_t n, const void *prev,
+__global__ __launch_bounds__(TB_BLOCK) __attribute__((amdgpu_waves_per_eu(TB_WAVES_PER_EU(S, D)))) void k_step_tbd(const Inst *__restrict__ tab, int32_t n, const void *prev,
                                                        const void *cur, void *outa, void *outb)
 {
     typedef typename V16<S>::T T;
@@ -104,8 +107,10 @@ __global__ __launch_bounds__(TB_BLOCK) void k_step_tbd(const Inst *__restrict__ 
             d[2] = G::lds(I.diag, x + Lx * row(-D));
             d[1] = G::lds(I.diag, x + Lx * row(1 - D));
         }
-        T rnp_n = G::ld(cur, (x + Lx * row(2 - D)) * C + c);
-        S dp_n = hd ? G::lds(I.diag, x + Lx * row(2 - D)) : (S)0;
+        // rows advance by one per iteration, tracked without divisions: yc = y0 + j + 2 - D (periodic)
+        uint32_t yc = row(2 - D);
+        T rnp_n = G::ld(cur, (x + Lx * yc) * C + c);
+        S dp_n = hd ? G::lds(I.diag, x + Lx * yc) : (S)0;
         T pv_n = (!first && s >= 1 && s + 1 < Wn) ? G::template ld_s<NT>(prev, (x + Lx * row(1 - D)) * C + c) : zero;
         T m2[D], m1[D];   // level k at rows (its current row) - 2 and - 1, k = 1 .. D-1
 #pragma unroll
@@ -119,10 +124,11 @@ __global__ __launch_bounds__(TB_BLOCK) void k_step_tbd(const Inst *__restrict__ 
             const T pv = pv_n;
             d[0] = dp_n;
             if (j + 1 < iters) {   // rows the next iteration needs
-                rnp_n = G::ld(cur, (x + Lx * row((int32_t)j + 3 - D)) * C + c);
-                dp_n = hd ? G::lds(I.diag, x + Lx * row((int32_t)j + 3 - D)) : (S)0;
+                const uint32_t yn = (yc + 1 == Ly) ? 0 : yc + 1;
+                rnp_n = G::ld(cur, (x + Lx * yn) * C + c);
+                dp_n = hd ? G::lds(I.diag, x + Lx * yn) : (S)0;
                 if (!first && s >= 1 && s + 1 < Wn)
-                    pv_n = G::template ld_s<NT>(prev, (x + Lx * row((int32_t)j + 2 - D)) * C + c);
+                    pv_n = G::template ld_s<NT>(prev, (x + Lx * yc) * C + c);
             }
             const uint32_t b = j & 1u, bp = b ^ 1u;
             lv_s[0][b][tid] = rn0;
@@ -156,7 +162,9 @@ __global__ __launch_bounds__(TB_BLOCK) void k_step_tbd(const Inst *__restrict__ 
                     if constexpr (SPIN) {
                         // bonds H~_{i,i+x}, H~_{i,i+y} stored at site i; the backward ones are the
                         // conjugates of the neighbour's forward bonds
-                        const uint32_t ry = row((int32_t)j + 2 - D - k), rym = row((int32_t)j + 1 - D - k);
+                        // rows yc - k and yc - k - 1; k + 1 <= D <= L_y / 2, so one wrap at most
+                        const uint32_t ry = (yc >= (uint32_t)k) ? yc - k : yc + Ly - k;
+                        const uint32_t rym = (ry == 0) ? Ly - 1 : ry - 1;
                         const S2 bxm = G::ldc(I.bond, (xm + Lx * ry) * 2 + 0);
                         const S2 bxp = G::ldc(I.bond, (x + Lx * ry) * 2 + 0);
                         const S2 bym = G::ldc(I.bond, (x + Lx * rym) * 2 + 1);
@@ -173,8 +181,8 @@ __global__ __launch_bounds__(TB_BLOCK) void k_step_tbd(const Inst *__restrict__ 
                 // stores and dots on the owned rows [y0, y1): level k is at row offset j - D - k + 2
                 const int32_t ro = (int32_t)j - D - k + 2;
                 if (own && ro >= 0 && ro < (int32_t)ns) {
-                    if (k == D - 1) G::template st_s<NT>(outa, (x + Lx * row(ro)) * C + c, v);
-                    if (k == D) G::template st_s<NT>(outb, (x + Lx * row(ro)) * C + c, v);
+                    if (k == D - 1) G::template st_s<NT>(outa, (x + Lx * (y0 + ro)) * C + c, v);
+                    if (k == D) G::template st_s<NT>(outb, (x + Lx * (y0 + ro)) * C + c, v);
                     acc[k - 1].add(v, k == 1 ? rn0 : m1[k - 1]);
                 }
                 if (k < D) lv_s[k][b][tid] = v;
@@ -188,6 +196,7 @@ __global__ __launch_bounds__(TB_BLOCK) void k_step_tbd(const Inst *__restrict__ 
             rn0 = rnp;
 #pragma unroll
             for (int q = D + 1; q > 0; --q) d[q] = d[q - 1];
+            yc = (yc + 1 == Ly) ? 0 : yc + 1;
         }
 #pragma unroll
         for (int k = 0; k < D; ++k)

@@ -176,10 +176,10 @@ def test_tblock_mode_is_used(tb):
     assert mode == 3
 
 
-@pytest.mark.parametrize("prec,spin,expect", [(kpm.F32, True, True), (kpm.F64, True, False),
+@pytest.mark.parametrize("prec,spin,expect", [(kpm.F32, True, True), (kpm.F64, True, True),
                                               (kpm.F32, False, True), (kpm.F64, False, True)])
 def test_tblock_default_by_precision_and_hopping(prec, spin, expect):
-    """The default (-1) blocks FP32 solves and FP64 real hopping, not FP64 spin hopping."""
+    """The default (-1) blocks 2D solves of both precisions and hopping kinds."""
     op = (_spin_lat if spin else _lat)(300, 40, 1.0, 17)
     with kpm.launch_settings(small=0, tblock=-1):
         h = kpm.Hamiltonian(op, 4.6, 0.0, prec)
