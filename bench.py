@@ -44,12 +44,12 @@ TB_KERNEL = {d: "k_step_tbd<float, OP_REAL2, %d> (%d step%s per launch)" % (d, d
              for d in range(1, 7)}
 
 
-def tb_depth(tblock, prec, C=16):
+def tb_depth(tblock, prec, C=16, spin=False):
     """Steps of the deepest pass of a temporally blocked solve for a KPM_LAUNCH_TBLOCK value (the
-    library's rule: -1 by precision, FP32 4 and FP64 3; 1 pairs; at most a quarter of the window
-    of 512 / C sites, C = 16-byte chunks per site)."""
+    library's rule: -1 gives 4 for FP32 real hopping and 3 otherwise; 1 pairs; at most a quarter of
+    the window of 512 / C sites, C = 16-byte chunks per site)."""
     if tblock < 0:
-        d = 3 if prec == 0 else 4
+        d = 3 if (prec == 0 or spin) else 4
     else:
         d = tblock if tblock >= 3 else 2
     return min(d, 512 // C // 4)

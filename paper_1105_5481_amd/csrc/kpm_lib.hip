@@ -30,7 +30,7 @@ int g_small = 1;                        // solves whose two vector blocks fit in
 int g_streaming = 2;                    // march: 0 cached, 1 non-temporal access of r_{n-1}/r_{n+1}, 2 by size
 int g_wave_mib = 224;                   // batched solves: vectors + operators per wave (MiB), 0 = one wave
 int g_tblock = -1;                      // 2D lattices: steps per pass (temporal blocking): 0 one, 1 two, 3..6,
-                                        // -1 by precision (tb_depth)
+                                        // -1 by precision and hopping (tb_depth)
 // Up to this much state (vectors + operator) r_{n+1} is stored cached, to be read back as r_n
 // from the 256 MiB Infinity Cache; measured on 64 x 64 x L_z spin lattices (c64, R = 32),
 // cached stores still win at 251 MiB (5.46 vs 5.00 TB/s; 234 MiB: 6.22 vs 5.01).
@@ -509,19 +509,20 @@ struct Plan {
 };
 
 // Halo (= steps of the deepest pass, 2 for pairs) of a temporally blocked solve.
-// Default (-1) by precision, measured on 2048^2 lattices: FP32 four steps (real R = 64:
-// 2.5x one step per pass; spin R = 16: 1.53x), FP64 three (four need over 150 VGPRs and
-// run slower; spin R = 8: 1.17x).
-int tb_depth(int prec)
+// Default (-1), measured on 2048^2 lattices: FP32 real hopping four steps (R = 64: 2.5x
+// one step per pass); FP32 spin hopping three (R = 16 / 32 / 64: 1.53x / 1.68x / 1.44x,
+// 1-10% faster than four); FP64 three (four need over 150 VGPRs and run slower; spin
+// R = 8: 1.27x).
+int tb_depth(int prec, int opk)
 {
-    if (g_tblock < 0) return prec == KPM_F64 ? 3 : 4;
+    if (g_tblock < 0) return (prec == KPM_F64 || opk == OP_SPIN2) ? 3 : 4;
     return g_tblock >= 3 ? g_tblock : 2;
 }
 // The halo actually used with C chunks per site: at most a quarter of the window of
 // TB_BLOCK / C sites, so that at least half of it is owned.
-int tb_halo(int prec, uint32_t C)
+int tb_halo(int prec, int opk, uint32_t C)
 {
-    return std::min<int>(tb_depth(prec), (int)(TB_BLOCK / C / 4));
+    return std::min<int>(tb_depth(prec, opk), (int)(TB_BLOCK / C / 4));
 }
 
 // Store kind for r_{n+1}: it is read again as r_n by the next step, so keep it
@@ -559,12 +560,12 @@ bool make_plan(const kpm_ham *h, int32_t M, int32_t R, int32_t vec, Plan &p, boo
         p.tiles = SMALL_WAVES;   // per-wave dot partials
         p.xcd = 0;
     } else if (allow_tb && g_tblock && g_march && (h->opk == OP_REAL2 || h->opk == OP_SPIN2) &&
-               TB_BLOCK % p.C == 0 && tb_halo(h->prec, p.C) >= 2 && h->L[0] >= TB_BLOCK / p.C &&
-               h->L[1] >= 2 * tb_halo(h->prec, p.C)) {
+               TB_BLOCK % p.C == 0 && tb_halo(h->prec, h->opk, p.C) >= 2 && h->L[0] >= TB_BLOCK / p.C &&
+               h->L[1] >= 2 * tb_halo(h->prec, h->opk, p.C)) {
         // several steps per pass: x-tiles of TB_BLOCK/C - 2 tbh owned sites, segments of rows
         p.mode = MODE_TB;
         p.nbuf = 4;
-        p.tbh = tb_halo(h->prec, p.C);
+        p.tbh = tb_halo(h->prec, h->opk, p.C);
         const uint32_t Tn = TB_BLOCK / p.C - 2 * (uint32_t)p.tbh;
         p.P = (uint32_t)h->L[0];
         p.Lm = (uint32_t)h->L[1];

@@ -83,6 +83,7 @@ __global__ __launch_bounds__(TB_BLOCK) __attribute__((amdgpu_waves_per_eu(TB_WAV
     const S hop = SPIN ? (S)0 : G::lds(I.hop, 0);
     const bool first = (n == 0);
     const T zero = (T)(S)0;
+    const T two = (T)(S)2;
     const ItemRange ir = item_range(I, I.nct, I.nseg);
     for (uint32_t it = ir.first; it < ir.count; it += ir.stride) {
         const uint32_t sl = it / ir.nu;
@@ -95,6 +96,7 @@ __global__ __launch_bounds__(TB_BLOCK) __attribute__((amdgpu_waves_per_eu(TB_WAV
         const bool own = s >= h && s < Wn - h && x0 + s - h < xend;
         const uint32_t y0 = sg * I.S, y1 = min(y0 + I.S, Ly), ns = y1 - y0;
         const uint32_t t = sg * I.nct + tx;
+        const uint32_t tl = (s >= 1) ? tid - C : tid, tr = (s + 1 < Wn) ? tid + C : tid;   // in-row neighbours
         Dots<S> acc[D];
         auto row = [&](int32_t off) { return (y0 + Ly + (uint32_t)off) % Ly; };   // y0 + off, periodic
         // level 0 (r_n): rows y-1, y, y+1 of the current iteration; diagonal d[q] of row y + 1 - q
@@ -137,46 +139,47 @@ __global__ __launch_bounds__(TB_BLOCK) __attribute__((amdgpu_waves_per_eu(TB_WAV
             cur_k[0] = rnp;
 #pragma unroll
             for (int k = 1; k <= D; ++k) {
-                T v = zero;
-                const bool ring = (k < D) ? (s >= (uint32_t)k && s + k < Wn) : own;
-                if (ring && j >= 2u * (uint32_t)(k - 1)) {
-                    // level k's row y - (k-1): its centre, neighbours (slots -x, +x, -y, +y) and the
-                    // value subtracted (r_{n+k-2} at that row)
-                    T centre, sub = zero;
-                    T nb[4];
-                    if (k == 1) {
-                        centre = rn0;
-                        nb[0] = lv_s[0][b][tid - C];
-                        nb[1] = lv_s[0][b][tid + C];
-                        nb[2] = rnm;
-                        nb[3] = rnp;
-                        sub = pv;
-                    } else {
-                        centre = m1[k - 1];
-                        nb[0] = lv_s[k - 1][bp][tid - C];
-                        nb[1] = lv_s[k - 1][bp][tid + C];
-                        nb[2] = m2[k - 1];
-                        nb[3] = cur_k[k - 1];
-                        sub = (k == 2) ? rnm : m2[k - 2 > 0 ? k - 2 : 0];
-                    }
-                    if constexpr (SPIN) {
-                        // bonds H~_{i,i+x}, H~_{i,i+y} stored at site i; the backward ones are the
-                        // conjugates of the neighbour's forward bonds
-                        // rows yc - k and yc - k - 1; k + 1 <= D <= L_y / 2, so one wrap at most
-                        const uint32_t ry = (yc >= (uint32_t)k) ? yc - k : yc + Ly - k;
-                        const uint32_t rym = (ry == 0) ? Ly - 1 : ry - 1;
-                        const S2 bxm = G::ldc(I.bond, (xm + Lx * ry) * 2 + 0);
-                        const S2 bxp = G::ldc(I.bond, (x + Lx * ry) * 2 + 0);
-                        const S2 bym = G::ldc(I.bond, (x + Lx * rym) * 2 + 1);
-                        const S2 byp = G::ldc(I.bond, (x + Lx * ry) * 2 + 1);
-                        const S hr[4] = {bxm[0], bxp[0], bym[0], byp[0]};
-                        const S hi[4] = {-bxm[1], bxp[1], -bym[1], byp[1]};
-                        v = apply_cplx<S, 4>(hd, d[k], centre, nb, hr, hi);
-                    } else {
-                        v = apply_real<S, 4>(hd, d[k], hop, centre, nb);
-                    }
-                    if (k > 1 || !first) v = (S)2 * v - sub;
+                // level k's row y - (k-1) on every site of the window: the levels above read only
+                // the sites at least k from the window edge, and only once the pipeline has filled
+                // (j >= 2(k-1)), so the values elsewhere are never used (edge neighbours are
+                // clamped to the site itself to keep the reads in the row)
+                // centre, neighbours (slots -x, +x, -y, +y), value subtracted (r_{n+k-2} at that row)
+                T centre, sub;
+                T nb[4];
+                if (k == 1) {
+                    centre = rn0;
+                    nb[0] = lv_s[0][b][tl];
+                    nb[1] = lv_s[0][b][tr];
+                    nb[2] = rnm;
+                    nb[3] = rnp;
+                    sub = pv;
+                } else {
+                    centre = m1[k - 1];
+                    nb[0] = lv_s[k - 1][bp][tl];
+                    nb[1] = lv_s[k - 1][bp][tr];
+                    nb[2] = m2[k - 1];
+                    nb[3] = cur_k[k - 1];
+                    sub = (k == 2) ? rnm : m2[k - 2 > 0 ? k - 2 : 0];
                 }
+                T v;
+                if constexpr (SPIN) {
+                    // bonds H~_{i,i+x}, H~_{i,i+y} stored at site i; the backward ones are the
+                    // conjugates of the neighbour's forward bonds
+                    // rows yc - k and yc - k - 1; k + 1 <= D <= L_y / 2, so one wrap at most
+                    const uint32_t ry = (yc >= (uint32_t)k) ? yc - k : yc + Ly - k;
+                    const uint32_t rym = (ry == 0) ? Ly - 1 : ry - 1;
+                    const S2 bxm = G::ldc(I.bond, (xm + Lx * ry) * 2 + 0);
+                    const S2 bxp = G::ldc(I.bond, (x + Lx * ry) * 2 + 0);
+                    const S2 bym = G::ldc(I.bond, (x + Lx * rym) * 2 + 1);
+                    const S2 byp = G::ldc(I.bond, (x + Lx * ry) * 2 + 1);
+                    const S hr[4] = {bxm[0], bxp[0], bym[0], byp[0]};
+                    const S hi[4] = {-bxm[1], bxp[1], -bym[1], byp[1]};
+                    v = apply_cplx<S, 4>(hd, d[k], centre, nb, hr, hi);
+                } else {
+                    v = apply_real<S, 4>(hd, d[k], hop, centre, nb);
+                }
+                // 2 v - sub in one rounding (2 v is exact), as the one-step kernel's expression
+                if (k > 1 || !first) v = __builtin_elementwise_fma(two, v, -sub);
                 cur_k[k] = v;
                 // stores and dots on the owned rows [y0, y1): level k is at row offset j - D - k + 2
                 const int32_t ro = (int32_t)j - D - k + 2;
