@@ -3,10 +3,11 @@
 Every stored value comes from the CPU oracle (oracle/), never from the HIP path:
 
   config2_oracle.txt   3D 64^3 spin hopping, M=1024, R=32 phase vectors (seed 1002, instance 0)
-  config4_oracle.txt   2D 2048^2 Anderson, first 256 of M=4096 moments, R=64 +-1 (seed 1004, instance 0);
-                       moments do not depend on how many are requested, so these are the
-                       first 256 moments of the full M=4096 solve
-  config3_oracle.txt   instances 0..3 of the 256-cube batch, M=512, R=16 phase (seed 1003, instance h)
+  config4_oracle.txt   2D 2048^2 Anderson, all M=4096 moments, R=64 +-1 (seed 1004, instance 0)
+                       (about 80 minutes of oracle time on 8 threads)
+  config3_h<h>_oracle.txt  instances h of the 256-cube batch, M=512, R=16 phase (seed 1003,
+                       instance h): 0..3 (the first four), and CONFIG3_EXTRA, which adds every
+                       L=48 cube (8, 78, 209) and cubes of L = 47, 46, 45, 44, 40, 21, 17
 
 The scale (a, b) is the oracle's Gershgorin bound with margin 0.01; it is stored (as hex) with
 the moments so the GPU tests use exactly the same operator.
@@ -23,6 +24,10 @@ sys.path.insert(0, ROOT)
 
 import oracle  # noqa: E402
 from paper_1105_5481_amd import workloads as wl  # noqa: E402
+
+
+# config-3 instances beyond the first four: indices of the L = 48 cubes and of a spread of sizes
+CONFIG3_EXTRA = (8, 78, 209, 12, 38, 19, 4, 7, 11, 29)
 
 
 def bounds(lat):
@@ -57,15 +62,14 @@ def main(which):
         print("config2", dt, flush=True)
     if "config4" in which:
         cfg = wl.config4()
-        a, b, mu, dt = run(cfg["lattice"], 256, cfg["R"], cfg["vec"], cfg["seed"], 0)
+        a, b, mu, dt = run(cfg["lattice"], cfg["M"], cfg["R"], cfg["vec"], cfg["seed"], 0)
         write(os.path.join(HERE, "config4_oracle.txt"),
-              {"workload": cfg["name"] + " (first 256 moments)", "M": 256, "R": cfg["R"], "vec": cfg["vec"],
+              {"workload": cfg["name"], "M": cfg["M"], "R": cfg["R"], "vec": cfg["vec"],
                "seed": cfg["seed"], "instance": 0, "a": a.hex(), "b": b.hex(), "oracle_seconds": f"{dt:.1f}"}, mu)
         print("config4", dt, flush=True)
     if "config3" in which:
         cfg = wl.config3()
-        lines = []
-        for h in range(4):
+        for h in list(range(4)) + list(CONFIG3_EXTRA):
             lat = cfg["lattices"][h]
             a, b, mu, dt = run(lat, cfg["M"], cfg["R"], cfg["vec"], cfg["seed"], h)
             write(os.path.join(HERE, f"config3_h{h}_oracle.txt"),

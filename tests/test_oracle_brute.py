@@ -99,13 +99,49 @@ def test_lattice_as_csr_gives_same_moments(oracle_mod):
     assert np.abs(m1 - m2).max() < 1e-13
 
 
-@pytest.mark.parametrize("case", _lattice_cases()[:3], ids=lambda c: "x".join(map(str, c[2])))
+def _discs(H):
+    """Gershgorin bounds written from a dense matrix: min/max over rows of Re H_ii -/+ sum_{j!=i} |H_ij|,
+    with |.| the complex modulus."""
+    off = np.abs(H).sum(axis=1) - np.abs(np.diag(H))
+    return (np.diag(H).real - off).min(), (np.diag(H).real + off).max()
+
+
+@pytest.mark.parametrize("case", _lattice_cases(), ids=lambda c: f"{c[0]}-{'x'.join(map(str, c[2]))}")
 def test_gershgorin_contains_spectrum(oracle_mod, case):
+    """Real and spin (complex) hopping: the oracle's bounds equal the disc bounds of the dense
+    matrix (Sec. II-A, below Eq. (tilde)) and enclose its spectrum.  For complex bonds the radius
+    uses the modulus, so a |Re| + |Im| radius would fail the equality."""
     kind, dim, L, t, hop, onsite, spinor, H = case
     lo, hi = oracle_mod.gershgorin_lattice(dim, L, t, hop, onsite, spinor)
     E = np.linalg.eigvalsh(H)
     assert lo <= E.min() + 1e-12 and E.max() <= hi + 1e-12
-    # Gershgorin discs written from the dense matrix
-    off = np.abs(H).sum(axis=1) - np.abs(np.diag(H))
-    assert lo == pytest.approx((np.diag(H).real - off).min(), abs=1e-12)
-    assert hi == pytest.approx((np.diag(H).real + off).max(), abs=1e-12)
+    if min(L) <= 2:
+        # a neighbour slot that wraps onto the site itself counts as an off-diagonal entry (each of
+        # the 2 dim slots adds |t| to the radius), where the dense matrix folds it into H_ii
+        assert kind == "real"
+        assert lo == pytest.approx(onsite.min() - 2 * dim * abs(t), abs=1e-12)
+        assert hi == pytest.approx(onsite.max() + 2 * dim * abs(t), abs=1e-12)
+        return
+    dlo, dhi = _discs(H)
+    assert lo == pytest.approx(dlo, abs=1e-12)
+    assert hi == pytest.approx(dhi, abs=1e-12)
+    if kind == "spin":
+        # the pin separates the modulus from the |Re| + |Im| reading
+        alt = (np.abs(H.real) + np.abs(H.imag)).sum(axis=1) - np.abs(np.diag(H))
+        assert abs((np.diag(H).real - alt).min() - dlo) > 1e-3
+
+
+@pytest.mark.parametrize("complex_values", [False, True])
+def test_gershgorin_csr_equals_dense_discs(oracle_mod, complex_values):
+    """CSR input (real and complex entries, Hermitian): the oracle's bounds equal the dense discs."""
+    csr = wl.random_hermitian_csr(64, 7, seed=19, complex_values=complex_values)
+    H = _ref.csr_dense(csr)
+    lo, hi = oracle_mod.gershgorin_csr(csr.row_ptr, csr.col, csr.val_re, csr.val_im)
+    dlo, dhi = _discs(H)
+    assert lo == pytest.approx(dlo, abs=1e-12)
+    assert hi == pytest.approx(dhi, abs=1e-12)
+    E = np.linalg.eigvalsh(H)
+    assert lo <= E.min() and E.max() <= hi
+    if complex_values:
+        alt = (np.abs(H.real) + np.abs(H.imag)).sum(axis=1) - np.abs(np.diag(H))
+        assert abs((np.diag(H).real - alt).min() - dlo) > 1e-3

@@ -129,3 +129,47 @@ def test_breakdown_truncates(oracle_mod):
     # the ring of 8 seen from a site: 5 distinct eigenvalues 2cos(2 pi q/8) with nonzero weight
     assert r["m"] == 5
     assert abs(r["theta_min"] + 2.0) < 1e-13 and abs(r["theta_max"] - 2.0) < 1e-13
+
+
+def _numpy_lanczos(Ht, v0, k):
+    """The three-term Lanczos process written out in numpy on a dense matrix: returns the basis
+    V (N x k), alpha, beta (k each) with H~ V = V T + beta_{k-1} v_k e_{k-1}^T."""
+    N = len(v0)
+    V = np.zeros((N, k + 1), dtype=complex)
+    al, be = np.zeros(k), np.zeros(k)
+    V[:, 0] = v0 / np.linalg.norm(v0)
+    for j in range(k):
+        u = Ht @ V[:, j]
+        al[j] = np.vdot(V[:, j], u).real
+        w = u - al[j] * V[:, j] - (be[j - 1] * V[:, j - 1] if j > 0 else 0.0)
+        be[j] = np.linalg.norm(w)
+        V[:, j + 1] = w / be[j]
+    return V[:, :k], al, be
+
+
+@pytest.mark.parametrize("case", _lattice_ops(), ids=lambda c: c[0])
+@pytest.mark.parametrize("k", [6, 12])
+def test_residual_bound_equals_dense_residual(oracle_mod, case, k):
+    """The residual bound r = beta_{m-1} |y_{m-1}| of each extreme Ritz pair (theta, y) is the norm
+    ||H~ V y - theta V y|| of its Ritz vector, with V the Lanczos basis built here by a numpy
+    Lanczos on the dense matrix from the same start vector (numpy's Philox).  Reading y_0 for
+    y_{m-1} would fail: the two differ by far more than the tolerance on these cases."""
+    name, op, H, vec = case
+    lam = np.linalg.eigvalsh(H)
+    a, b = (lam[-1] - lam[0]) / 1.9, (lam[-1] + lam[0]) / 2
+    Ht = (H - b * np.eye(len(H))) / a
+    al, be = _lanczos(oracle_mod, op, a, b, k, vec)
+    r = oracle_mod.lanczos_bounds(al, be, 1.0, 0.0, pad=0.0)
+    assert r["m"] == k
+    xi = _ref.start_vectors_numpy(vec, 9, 2, len(H), 1)[0]
+    V, al_np, be_np = _numpy_lanczos(Ht, xi, k)
+    assert np.max(np.abs(al_np - al)) < 1e-12 and np.max(np.abs(be_np - be)) < 1e-12
+    T = np.diag(al) + np.diag(be[:-1], 1) + np.diag(be[:-1], -1)
+    th, Y = np.linalg.eigh(T)
+    for col, key, tkey in ((0, "r_min", "theta_min"), (k - 1, "r_max", "theta_max")):
+        y = Y[:, col]
+        x = V @ y
+        dense = np.linalg.norm(Ht @ x - th[col] * x)
+        assert abs(r[tkey] - th[col]) < 1e-12
+        assert abs(r[key] - dense) <= 1e-9 * max(dense, 1e-3), (name, key, r[key], dense)
+        assert abs(be[k - 1] * abs(y[0]) - dense) > 1e-6, (name, key)
