@@ -5,9 +5,10 @@ A timed "step" is one pass of the whole hot path over one input: operator prepar
 H~ = (H - b)/a from device-resident inputs, the start vectors, floor(M/2) fused recursion
 steps with their dot products, the moment reduction, and the Jackson-damped DoS.
 
-Default workload: 3D cubic 64^3 lattice, periodic, spin hopping from seeded classical spins
-uniform on the sphere, M = 1024 moments, R = 32 random-phase vectors, complex64 recursion
-with FP64 moment accumulation; the plain FP64 (complex128) path is timed beside it.
+Default workload: 2D square 2048^2 lattice, periodic, Anderson disorder uniform[-1, 1],
+M = 4096 moments, R = 64 +-1 vectors as one block, FP32 recursion with FP64 moment
+accumulation; the plain FP64 path is timed beside it.  The cache-resident 3D 64^3 spin
+lattice (complex64, M = 1024, R = 32) and a short serving stream are reported on the same line.
 
 Prints one JSON line.  `--gpus N` with N > 1 is refused: this build measures one GPU.
 """
@@ -267,8 +268,10 @@ def algorithmic_bytes_per_step(N, R, cplx, esz, has_diag, bonds_per_site):
 def kernel_source_digest():
     import hashlib
     h = hashlib.sha256()
-    for f in ("kpm_kernels.hpp", "kpm_device.hpp", "kpm_tblock.hpp"):
-        h.update(open(os.path.join(ROOT, "paper_1105_5481_amd", "csrc", f), "rb").read())
+    csrc = os.path.join(ROOT, "paper_1105_5481_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):     # every kernel and the host code that shapes their launches
+        if f.endswith((".hpp", ".hip")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -432,7 +435,7 @@ def cpu_baseline(lat, a, b, vec, seed):
     import oracle
     oracle.build()
     threads = oracle.max_threads()
-    Ms, Rs = (1024, 32) if lat.N <= 300000 else (64, 8)
+    Ms, Rs = (1024, 32) if lat.N <= 300000 else (128, 16)
 
     def run(M_, R_, nthreads):
         t0 = time.perf_counter()
@@ -442,12 +445,162 @@ def cpu_baseline(lat, a, b, vec, seed):
 
     dt = run(Ms, Rs, threads)
     # one thread, on a smaller sample, median of 3 runs
-    M1, R1 = (64, 4) if lat.N <= 300000 else (16, 4)
+    M1, R1 = (64, 4) if lat.N <= 300000 else (16, 2)
     d1 = sorted(run(M1, R1, 1) for _ in range(3))[1]
     return {"value": lat.N * Ms * Rs / dt, "unit": UNIT, "cores": threads, "kind": "oracle",
             "sample": f"full {lat.N}-site lattice, M={Ms} moments, R={Rs} vectors ({dt:.1f} s)",
             "single_thread": {"value": lat.N * M1 * R1 / d1, "cores": 1,
                               "sample": f"M={M1}, R={R1}, median of 3 runs ({d1:.2f} s each)"}}
+
+
+
+def tb_pass_bytes(N, R, cplx, esz, has_diag, depth):
+    """Bytes one temporally blocked pass of `depth` >= 2 steps must move at least: read r_{n-1}
+    and r_n, write r_{n+depth-1} and r_{n+depth} (4 N R e), plus the diagonal once per step."""
+    e = esz * (2 if cplx else 1)
+    return 4 * N * R * e + depth * N * (esz if has_diag else 0)
+
+
+def bench_lattice(args, workload, steps, warmup, fp64=True, cpu=True):
+    """One lattice workload (config 2 or config 4): `steps` timed passes of the whole path
+    (operator preparation, start vectors, recursion, moments, DoS) in FP32 / complex64, and the
+    plain FP64 path beside it."""
+    import numpy as np
+    import torch
+    import paper_1105_5481_amd as kpm
+    from paper_1105_5481_amd import workloads as wl
+    dev = "cuda"
+    stream = torch.cuda.current_stream()
+    cfg = wl.config2() if workload == "config2" else wl.config4()
+    lat, M, R, vec, seed = cfg["lattice"], cfg["M"], cfg["R"], cfg["vec"], cfg["seed"]
+    cplx = lat.hop == wl.HOP_SPIN or vec == wl.VEC_PHASE
+    K_dos = 2 * M
+    N = lat.N
+    log(f"bench: workload {cfg['name']} N={N} M={M} R={R}")
+
+    # device-resident inputs and the descriptor pointing at them
+    desc, keep = kpm._desc_for(lat, dev)
+    lo, hi = kpm.gershgorin(lat)
+    a, b = kpm.scale_from_bounds(lo, hi, 0.01)
+
+    def make_solver(prec):
+        h = kpm.Hamiltonian(lat, a, b, prec)
+        nbytes = h.workspace_bytes(M, R, vec)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        mu = torch.empty(M, dtype=torch.float64, device=dev)
+        om = torch.empty(K_dos, dtype=torch.float64, device=dev)
+        rho = torch.empty(K_dos, dtype=torch.float64, device=dev)
+        return h, ws, nbytes, mu, om, rho
+
+    L = kpm.lib()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    K = M // 2
+    solve_mode = {}
+
+    def run_step(state, instance, ev=None):
+        h, ws, nbytes, mu, om, rho = state
+        kpm._check(L.kpm_update(h.handle, ctypes.byref(desc), a, b, sp), "kpm_update")            # a0
+        s = ctypes.c_void_p()
+        kpm._check(L.kpm_solve_begin(h.handle, M, R, vec, seed, instance, ws.data_ptr(), nbytes, sp,
+                                     ctypes.byref(s)), "kpm_solve_begin")                         # a1
+        solve_mode[h.prec] = L.kpm_solve_mode(s)
+        if ev is not None:
+            ev[0].record(stream)
+        rem = ctypes.c_int32()
+        kpm._check(L.kpm_solve_advance(s, K, sp, ctypes.byref(rem)), "kpm_solve_advance")           # a2-a3, a5
+        if ev is not None:
+            ev[1].record(stream)
+        kpm._check(L.kpm_solve_finish(s, mu.data_ptr(), sp), "kpm_solve_finish")                   # a4
+        L.kpm_solve_free(s)
+        kpm._check(L.kpm_dos(mu.data_ptr(), M, 1, K_dos, a, b, om.data_ptr(), rho.data_ptr(), sp), "kpm_dos")
+
+    def timed(state, steps_, warmup_, tag):
+        for w in range(warmup_):
+            run_step(state, 1000 + w)
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps_)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s_ in range(steps_):
+            run_step(state, s_, evs[s_])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rec_ms = sum(e0.elapsed_time(e1) for e0, e1 in evs) / steps_       # the recursion launches of a step
+        log(f"bench: {workload} {tag}: {dt / steps_ * 1e3:.3f} ms/step, recursion {rec_ms:.3f} ms/step")
+        return dt, rec_ms
+
+    s32 = make_solver(kpm.F32)
+    dt32, rec32 = timed(s32, steps, warmup, "c64" if cplx else "f32")
+    ms_per_step = dt32 / steps * 1e3
+    updates = float(N) * M * R
+    value = updates / (dt32 / steps)
+    tblocked = solve_mode.get(kpm.F32) == 3
+    chunks = -(-R * (2 if cplx else 1) // 4)  # 16-byte chunks per site (FP32)
+    depth = tb_depth(kpm.get_launch()["tblock"], kpm.F32, chunks) if tblocked else 1   # recursion steps per launch
+    nrec = K if tblocked else K - 1          # begin runs step 0 except with temporal blocking
+    step_us = rec32 * 1e3 / nrec             # per recursion step
+    launch_us = step_us * depth
+    bonds = lat.dim if lat.hop == wl.HOP_SPIN else 0
+    mode = "march" if kpm.get_launch()["march"] else "flat"
+    kernel_name = "k_step_%s<float, %s>" % (mode, "OP_SPIN3" if bonds else "OP_REAL2")
+    if tblocked:
+        kernel_name = TB_KERNEL[depth]
+    has_diag = s32[0].b != 0.0 or lat.onsite is not None
+    bytes_step = algorithmic_bytes_per_step(N, R, cplx, 4, has_diag, bonds)   # the method's 3 streams
+    traffic_step = measured_traffic(workload, kernel_name)
+    if tblocked:
+        # the blocked pass moves 4 vector streams for `depth` steps, plus the halo re-reads of its
+        # tiles; its rate against the HBM peak is counted from the bytes it moves (rocprof counters
+        # of the same kernel source), or, without a current counter record, from its minimum
+        min_launch = tb_pass_bytes(N, R, cplx, 4, has_diag, depth)
+        moved_launch = traffic_step * depth if traffic_step else min_launch
+        achieved = moved_launch / (launch_us * 1e-6) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS,
+                "traffic": traffic_step * depth if traffic_step else None,
+                "kernel": kernel_name, "bytes_per_launch": moved_launch,
+                "bytes_basis": ("rocprof FETCH_SIZE/WRITE_SIZE of this kernel source per launch" if traffic_step
+                                else "blocked-pass minimum: 4 vector streams + diagonal per launch"),
+                "min_bytes_per_launch": min_launch, "avg_launch_us": launch_us,
+                "steps_per_launch": depth,
+                "effective_3stream": {
+                    "achieved": bytes_step * depth / (launch_us * 1e-6) / 1e9,
+                    "frac": bytes_step * depth / (launch_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                    "bytes_per_launch": bytes_step * depth,
+                    "note": "the method's 3 vector streams per step for each of the launch's steps: "
+                            "bytes the blocked pass avoids, not bytes it moves"}}
+    else:
+        achieved = bytes_step / (step_us * 1e-6) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_step, "kernel": kernel_name,
+                "bytes_per_launch": bytes_step, "avg_launch_us": step_us}
+    # same start vectors for the FP32 / FP64 comparison
+    run_step(s32, 0)
+    mu32 = s32[3].cpu().numpy()
+
+    out = {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64" if cplx else "f32", "data": "synthetic",
+        "config": {"workload": WORKLOAD_TEXT[workload],
+                   "N": N, "M": M, "R": R, "recursion": "complex64" if cplx else "float32", "moments": "fp64"},
+        "roofline": roof,
+    }
+    if fp64:
+        s64 = make_solver(kpm.F64)
+        dt64, rec64 = timed(s64, args.fp64_steps, 1, "c128" if cplx else "f64")
+        v64 = updates / (dt64 / args.fp64_steps)
+        run_step(s64, 0)
+        mu64 = s64[3].cpu().numpy()
+        out["fp64_path"] = {"value": v64, "unit": UNIT, "ms_per_step": dt64 / args.fp64_steps * 1e3,
+                            "dtype": "c128" if cplx else "f64", "speedup_fp32_over_fp64": value / v64,
+                            "fp32_max_abs_err_vs_fp64": float(np.abs(mu32 - mu64).max())}
+        s64[0].free()
+    if cpu:
+        log("bench: timing the oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(lat, a, b, vec, seed)
+    s32[0].free()
+    return out
 
 
 def main():
@@ -481,9 +634,13 @@ def main():
     ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/traffic.json for --workload from the FETCH_SIZE and WRITE_SIZE runs "
                          "of one profiled solve (--steps 1 --warmup 0 --calib-copy) and exit")
-    ap.add_argument("--workload", default="config2",
+    ap.add_argument("--workload", default="config4",
                     choices=["config2", "config3", "config4", "config5", "dense", "aux"],
-                    help="config2 (the measured workload), config3 (256-cube batch), config4 (2D 2048^2, R=64, real FP32), config5 (serving record)")
+                    help="config4 (2D 2048^2, R=64, real FP32: the largest single-lattice workload, default), "
+                         "config2 (3D 64^3 spin, c64, cache-resident), config3 (256-cube batch), "
+                         "config5 (serving record), dense (matrix-core dense H), aux (Lanczos, Green's functions)")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="config4: skip the cache-resident 3D workload reported beside it")
     args = ap.parse_args()
 
     if args.pmc_summary:
@@ -494,7 +651,7 @@ def main():
         cfg = getattr(wl, args.workload)()
         kern = {"config2": "k_step_march<float, OP_SPIN3>", "config3": CONFIG3_KERNEL,
                 "config4": TB_KERNEL[tb_depth(kpm_default_tblock(), 1)]}[args.workload]
-        extra = {"config2": "--no-fp64 --no-cpu-baseline --no-serve ", "config4": "--no-fp64 --no-cpu-baseline --no-serve ",
+        extra = {"config2": "--no-fp64 --no-cpu-baseline --no-serve ", "config4": "--no-fp64 --no-cpu-baseline --no-serve --no-secondary ",
                  "config3": ""}[args.workload]
         cmds = [f"rocprofv3 --pmc {c} --output-format csv -d <dir> -o p -- python3 bench.py --workload "
                 f"{args.workload} --steps 1 --warmup 0 {extra}--calib-copy" for c in ("FETCH_SIZE", "WRITE_SIZE")]
@@ -532,9 +689,6 @@ def main():
                    streaming=None if args.streaming < 0 else args.streaming,
                    wave_mib=None if args.wave_mib < 0 else args.wave_mib,
                    tblock=None if args.tblock < 0 else args.tblock)
-    dev = "cuda"
-    stream = torch.cuda.current_stream()
-
     if args.workload == "config5":
         # the serving record alone: FP32 continuous batching vs the plain FP64 FCFS path
         sv = serving_leg(args.serve_requests, args.serve_logn_max, args.serve_load, fp64_stable=args.serve_fp64_stable)
@@ -551,125 +705,19 @@ def main():
     if args.workload == "aux":
         print(json.dumps(bench_aux(args, log)), flush=True)
         return
-    cfg = wl.config2() if args.workload == "config2" else wl.config4()
-    lat, M, R, vec, seed = cfg["lattice"], cfg["M"], cfg["R"], cfg["vec"], cfg["seed"]
-    cplx = lat.hop == wl.HOP_SPIN or vec == wl.VEC_PHASE
-    K_dos = 2 * M
-    N = lat.N
-    log(f"bench: workload {cfg['name']} N={N} M={M} R={R}")
-
-    # device-resident inputs and the descriptor pointing at them
-    desc, keep = kpm._desc_for(lat, dev)
-    lo, hi = kpm.gershgorin(lat)
-    a, b = kpm.scale_from_bounds(lo, hi, 0.01)
-
-    def make_solver(prec):
-        h = kpm.Hamiltonian(lat, a, b, prec)
-        nbytes = h.workspace_bytes(M, R, vec)
-        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
-        mu = torch.empty(M, dtype=torch.float64, device=dev)
-        om = torch.empty(K_dos, dtype=torch.float64, device=dev)
-        rho = torch.empty(K_dos, dtype=torch.float64, device=dev)
-        return h, ws, nbytes, mu, om, rho
-
-    L = kpm.lib()
-    sp = ctypes.c_void_p(stream.cuda_stream)
-    K = M // 2
-
-    solve_mode = {}
-
-    def run_step(state, instance, ev=None):
-        h, ws, nbytes, mu, om, rho = state
-        kpm._check(L.kpm_update(h.handle, ctypes.byref(desc), a, b, sp), "kpm_update")            # a0
-        s = ctypes.c_void_p()
-        kpm._check(L.kpm_solve_begin(h.handle, M, R, vec, seed, instance, ws.data_ptr(), nbytes, sp,
-                                     ctypes.byref(s)), "kpm_solve_begin")                         # a1
-        solve_mode[h.prec] = L.kpm_solve_mode(s)
-        if ev is not None:
-            ev[0].record(stream)
-        rem = ctypes.c_int32()
-        kpm._check(L.kpm_solve_advance(s, K, sp, ctypes.byref(rem)), "kpm_solve_advance")           # a2-a3, a5
-        if ev is not None:
-            ev[1].record(stream)
-        kpm._check(L.kpm_solve_finish(s, mu.data_ptr(), sp), "kpm_solve_finish")                   # a4
-        L.kpm_solve_free(s)
-        kpm._check(L.kpm_dos(mu.data_ptr(), M, 1, K_dos, a, b, om.data_ptr(), rho.data_ptr(), sp), "kpm_dos")
-
-    def timed(state, steps, warmup, tag):
-        for w in range(warmup):
-            run_step(state, 1000 + w)
-        torch.cuda.synchronize()
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for s_ in range(steps):
-            run_step(state, s_, evs[s_])
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        rec_ms = sum(e0.elapsed_time(e1) for e0, e1 in evs) / steps       # K-1 recursion launches per step
-        log(f"bench: {tag}: {dt / steps * 1e3:.3f} ms/step, recursion {rec_ms:.3f} ms/step")
-        return dt, rec_ms
-
-    s32 = make_solver(kpm.F32)
-    dt32, rec32 = timed(s32, args.steps, args.warmup, "c64")
-    ms_per_step = dt32 / args.steps * 1e3
-    updates = float(N) * M * R
-    value = updates / (dt32 / args.steps)
-    tblocked = solve_mode.get(kpm.F32) == 3
-    chunks = -(-R * (2 if cplx else 1) // 4)  # 16-byte chunks per site (FP32)
-    depth = tb_depth(kpm.get_launch()["tblock"], kpm.F32, chunks) if tblocked else 1   # recursion steps per launch
-    nrec = K if tblocked else K - 1          # begin runs step 0 except with temporal blocking
-    step_us = rec32 * 1e3 / nrec             # per recursion step
-    bonds = lat.dim if lat.hop == wl.HOP_SPIN else 0
-    mode = "march" if kpm.get_launch()["march"] else "flat"
-    kernel_name = "k_step_%s<float, %s>" % (mode, "OP_SPIN3" if bonds else "OP_REAL2")
-    if tblocked:
-        kernel_name = TB_KERNEL[depth]
-    bytes_step = algorithmic_bytes_per_step(N, R, cplx, 4, s32[0].b != 0.0 or lat.onsite is not None, bonds)
-    achieved = bytes_step / (step_us * 1e-6) / 1e9
-    # same start vectors for the c64 / c128 comparison
-    run_step(s32, 0)
-    mu32 = s32[3].cpu().numpy()
-
-    out = {
-        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "c64" if cplx else "f32", "data": "synthetic",
-        "config": {"workload": WORKLOAD_TEXT[args.workload],
-                   "N": N, "M": M, "R": R, "recursion": "complex64" if cplx else "float32", "moments": "fp64"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(args.workload, kernel_name),
-                     "kernel": kernel_name,
-                     "bytes_per_launch": bytes_step * depth,
-                     "avg_launch_us": step_us * depth},
-    }
-    if tblocked:
-        out["roofline"]["note"] = (f"{depth} recursion steps per launch: bytes_per_launch counts the method's 3 vector "
-                                   f"streams for each of them; the kernel itself moves 4 vector streams per launch "
-                                   f"(plus halo re-reads)")
-
-    if not args.no_fp64:
-        s64 = make_solver(kpm.F64)
-        dt64, rec64 = timed(s64, args.fp64_steps, 1, "c128")
-        v64 = updates / (dt64 / args.fp64_steps)
-        run_step(s64, 0)
-        mu64 = s64[3].cpu().numpy()
-        import numpy as np
-        out["fp64_path"] = {"value": v64, "unit": UNIT, "ms_per_step": dt64 / args.fp64_steps * 1e3,
-                            "dtype": "c128" if cplx else "f64", "speedup_fp32_over_fp64": value / v64,
-                            "fp32_max_abs_err_vs_fp64": float(np.abs(mu32 - mu64).max())}
-        s64[0].free()
-
+    out = bench_lattice(args, args.workload, args.steps, args.warmup, fp64=not args.no_fp64,
+                        cpu=not args.no_cpu_baseline)
+    if args.workload == "config4" and not args.no_secondary:
+        # the cache-resident 3D workload beside the headline (its state fits the Infinity Cache)
+        sec = bench_lattice(args, "config2", max(args.steps, 10), args.warmup, fp64=not args.no_fp64, cpu=False)
+        out["cache_resident"] = {k: sec[k] for k in ("value", "unit", "ms_per_step", "dtype", "config", "roofline")}
+        if "fp64_path" in sec:
+            out["cache_resident"]["fp64_path"] = sec["fp64_path"]
+        out["cache_resident"]["note"] = ("3D 64^3 spin lattice: its 134 MiB complex64 state fits the 256 MiB "
+                                         "Infinity Cache, so the rate is partly cache bandwidth")
     if not args.no_serve:
         log("bench: serving leg")
         out["serving"] = serving_leg(args.serve_requests, args.serve_logn_max, args.serve_load[0])
-
-    if not args.no_cpu_baseline:
-        log("bench: timing the oracle on a bounded sample")
-        out["cpu_baseline"] = cpu_baseline(lat, a, b, vec, seed)
-
-    s32[0].free()
     print(json.dumps(out), flush=True)
 
 

@@ -100,7 +100,9 @@ typedef struct {
 typedef struct kpm_ham kpm_ham;     /* opaque: the scaled operator in device memory */
 typedef struct kpm_solve kpm_solve; /* opaque: one solve whose state lives in a workspace */
 
-/* Human-readable name of a status code (static string). */
+/* Human-readable name of a status code (static string; never NULL, "unknown
+ * status" for a value outside kpm_status).  A diagnostic of this library, not an
+ * operation of the method. */
 const char *kpm_status_string(kpm_status st);
 
 /* Name of the last HIP runtime error a call of this thread ran into (behind
@@ -179,8 +181,15 @@ kpm_status kpm_build(const kpm_ham_desc *desc, double a, double b, int32_t prec,
  * For Monte-Carlo loops over perturbed spin textures and for serving. */
 kpm_status kpm_update(kpm_ham *h, const kpm_ham_desc *desc, double a, double b, void *stream);
 
-/* Release the operator's device memory (the caller synchronises first). */
+/* Release the device memory kpm_build allocated for the operator H~ of
+ * Eq. (tilde), and the handle itself.  The caller synchronises the streams
+ * that used it first.  NULL is ignored. */
 void kpm_free(kpm_ham *h);
+
+/* The rescaling H~ = (H - b)/a (Eq. (tilde)) the operator was built or last
+ * updated with: *a = alpha_-, *b = alpha_+ exactly as passed (no rounding of a
+ * or b is applied in either precision).  KPM_ERR_INVALID_ARG for NULL. */
+kpm_status kpm_ham_get_scale(const kpm_ham *h, double *a, double *b);
 
 /* Number of sites N of the operator, or -1 for NULL. */
 int64_t kpm_ham_dim(const kpm_ham *h);
@@ -189,9 +198,11 @@ int64_t kpm_ham_dim(const kpm_ham *h);
  *   a = (E_hi - E_lo)/(2 - eps),  b = (E_hi + E_lo)/2.   (Host arithmetic only.) */
 kpm_status kpm_scale_from_bounds(double e_lo, double e_hi, double eps, double *a, double *b);
 
-/* Bytes of device workspace one solve with M moments and R vectors needs
- * (the two vector blocks, per-tile reduction partials and the dot products);
- * 0 on invalid arguments. */
+/* Bytes of device workspace one solve with M moments and R vectors needs:
+ * the vector blocks of the recursion of Eq. (rn) (r_{n-1} and r_n, N x R
+ * values each; four blocks for temporally blocked 2D solves), the per-work-item
+ * partials of the dot products of Eq. (munr), and the floor(M/2) + 1 dot sums.
+ * 0 on invalid arguments.  A pure host computation from the handle's shape. */
 size_t kpm_workspace_bytes(const kpm_ham *h, int32_t M, int32_t R, int32_t vec);
 
 /* All M moments mu_0..mu_{M-1} (Eq. (munr) through the doubling identities)
@@ -218,12 +229,20 @@ kpm_status kpm_solve_finish(kpm_solve *s, double *mu_dev, void *stream);
 void kpm_solve_free(kpm_solve *s);
 /* How the solve's recursion runs: 0 flat kernels (one step per launch), 1 march
  * kernels (one step per launch), 2 whole recursion in one workgroup (done at
- * begin), 3 temporal blocking (two steps per launch); -1 for NULL. */
+ * begin), 3 temporal blocking (1 to 6 steps per launch, KPM_LAUNCH_TBLOCK);
+ * -1 for NULL. */
 int32_t kpm_solve_mode(const kpm_solve *s);
 
-/* Many independent solves in one set of launches (each recursion step of every
- * instance runs in one grid; the reduction partials are per tile, so every
- * instance's moments are bitwise equal to the same solve run alone).  All
+/* Many independent solves in one set of launches: each instance computes the
+ * moments of Eq. (munr) by the recursion of Eq. (rn) exactly as kpm_moments
+ * does (the paper runs one operator per launch; running many operators of
+ * uneven size in shared launches is this library's extension).  Each
+ * recursion step of every instance runs in one grid; the reduction partials
+ * are per work item, so every instance's moments are bitwise equal to the same
+ * solve run alone.  Instances run in waves whose state fits the Infinity Cache
+ * (KPM_LAUNCH_WAVE_MIB).  Errors as kpm_moments; on an argument error nothing
+ * is enqueued.  The workspace is kpm_workspace_bytes_batched bytes, 256-byte
+ * aligned, caller-owned, and used until the stream reaches the end.  All
  * handles must share the recursion precision and, per launch group, the
  * operator class; mixed classes are grouped internally.  Arrays of length
  * `count`: h, M, R, seed, instance, mu_dev (device arrays of M[i] doubles). */

@@ -69,6 +69,7 @@ def lib():
         "kpm_free": (None, [P]),
         "kpm_update": (i32, [P, pdesc, f64, f64, P]),
         "kpm_ham_dim": (i64, [P]),
+        "kpm_ham_get_scale": (i32, [P, P, P]),
         "kpm_workspace_bytes": (sz, [P, i32, i32, i32]),
         "kpm_moments": (i32, [P, i32, i32, i32, u64, u64, P, sz, P, P]),
         "kpm_solve_begin": (i32, [P, i32, i32, i32, u64, u64, P, sz, P, P]),
@@ -283,6 +284,12 @@ class Hamiltonian:
     @property
     def N(self) -> int:
         return int(lib().kpm_ham_dim(self.handle))
+
+    def scale(self):
+        """(a, b) of H~ = (H - b)/a as the operator holds them (kpm_ham_get_scale)."""
+        a, b = ctypes.c_double(), ctypes.c_double()
+        _check(lib().kpm_ham_get_scale(self.handle, ctypes.byref(a), ctypes.byref(b)), "kpm_ham_get_scale")
+        return a.value, b.value
 
     def workspace_bytes(self, M: int, R: int, vec: int) -> int:
         n = lib().kpm_workspace_bytes(self.handle, M, R, vec)

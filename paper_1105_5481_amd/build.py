@@ -1,6 +1,7 @@
 """Build libkpm.so for gfx950 with hipcc (in-tree, next to this file)."""
 from __future__ import annotations
 
+import glob
 import os
 import subprocess
 import sys
@@ -8,8 +9,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "kpm_lib.hip")
-DEPS = [SRC, os.path.join(HERE, "csrc", "kpm_kernels.hpp"), os.path.join(HERE, "csrc", "kpm_device.hpp"),
-        os.path.join(ROOT, "include", "kpm.h")]
+DEPS = sorted(glob.glob(os.path.join(HERE, "csrc", "*.hpp")) + glob.glob(os.path.join(HERE, "csrc", "*.hip"))
+              + glob.glob(os.path.join(ROOT, "include", "*.h")))
 LIB = os.path.join(HERE, "libkpm.so")
 
 HIPCC_FLAGS = [

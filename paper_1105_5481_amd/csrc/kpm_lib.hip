@@ -1019,6 +1019,14 @@ void kpm_free(kpm_ham *h)
 
 int64_t kpm_ham_dim(const kpm_ham *h) { return h ? h->N : -1; }
 
+kpm_status kpm_ham_get_scale(const kpm_ham *h, double *a, double *b)
+{
+    if (!h || !a || !b) return KPM_ERR_INVALID_ARG;
+    *a = h->a;
+    *b = h->b;
+    return KPM_OK;
+}
+
 size_t kpm_workspace_bytes(const kpm_ham *h, int32_t M, int32_t R, int32_t vec)
 {
     Plan p;

@@ -56,39 +56,54 @@ def test_config2_full():
     assert l1 <= bound * (1 + 1e-9) + 1e-15
 
 
-def test_config4_prefix():
-    """The full M=4096 FP32 solve; its first 256 moments against the oracle's M=256 run."""
+def test_config4_full():
+    """The full M=4096 FP32 solve (temporally blocked passes) against the oracle on every stored
+    moment, its DoS L1 error against the bound, and the FP64 path (three-step passes) on the same
+    moments at REL64."""
     hdr, ref, a, b = golden("config4_oracle.txt")
     cfg = wl.config4()
     lat = cfg["lattice"]
+    Mref = len(ref)
+    print(f"  config4 golden: {Mref} of {cfg['M']} moments", flush=True)
     g32 = gu.gpu_moments(lat, a, b, kpm.F32, cfg["M"], cfg["R"], cfg["vec"], cfg["seed"], 0)
-    gu.assert_fp32(g32[:256], ref, "config4 f32 (prefix of M=4096)")
+    gu.assert_fp32(g32[:Mref], ref, f"config4 f32 (first {Mref} of M=4096)")
     assert np.all(np.isfinite(g32)) and np.abs(g32).max() <= 1.0 + 1e-6
-    g64 = gu.gpu_moments(lat, a, b, kpm.F64, 256, cfg["R"], cfg["vec"], cfg["seed"], 0)
-    gu.assert_fp64(g64, ref, "config4 f64")
+    if Mref == cfg["M"]:
+        l1, bound = dos_l1(g32, ref, 2 * cfg["M"], a, b)
+        print(f"  config4 f32 DoS L1 error {l1:.3e} (bound {bound:.3e})", flush=True)
+        assert l1 <= bound * (1 + 1e-9) + 1e-15
+    g64 = gu.gpu_moments(lat, a, b, kpm.F64, Mref, cfg["R"], cfg["vec"], cfg["seed"], 0)
+    gu.assert_fp64(g64, ref, f"config4 f64 M={Mref}")
 
 
 def test_config3_batch():
-    """All 256 cubes in one batched c64 solve; instances 0..3 against the oracle, and each equal
-    (bitwise) to the same instance solved alone."""
+    """All 256 cubes in one batched c64 solve; every instance with stored oracle moments (the first
+    four, every L=48 cube and a spread of other sizes) against the oracle, each equal (bitwise) to
+    the same instance solved alone, and its c128 path against the oracle at REL64."""
+    from tests.golden.make_golden import CONFIG3_EXTRA
     cfg = wl.config3()
     M, R, vec, seed = cfg["M"], cfg["R"], cfg["vec"], cfg["seed"]
-    refs = [golden(f"config3_h{h}_oracle.txt") for h in range(4)]
+    checked = [h for h in list(range(4)) + list(CONFIG3_EXTRA)
+               if os.path.exists(os.path.join(GOLDEN, f"config3_h{h}_oracle.txt"))]
+    assert len(checked) >= 4
+    refs = {h: golden(f"config3_h{h}_oracle.txt") for h in checked}
     hs = []
     for h, lat in enumerate(cfg["lattices"]):
-        if h < 4:
+        if h in refs:
             a, b = refs[h][2], refs[h][3]
         else:
             lo, hi = kpm.gershgorin(lat)
             a, b = kpm.scale_from_bounds(lo, hi, 0.01)
         hs.append(kpm.Hamiltonian(lat, a, b, kpm.F32))
     mus = [m.cpu().numpy() for m in kpm.moments_batched(hs, M, R, vec, [seed] * len(hs), list(range(len(hs))))]
-    for h in range(4):
-        gu.assert_fp32(mus[h], refs[h][1], f"config3 batched c64 instance {h} (L={cfg['lattices'][h].L[0]})")
+    for h in checked:
+        L = cfg["lattices"][h].L[0]
+        gu.assert_fp32(mus[h], refs[h][1], f"config3 batched c64 instance {h} (L={L})")
         solo = kpm.moments(hs[h], M, R, vec, seed, h).cpu().numpy()
         assert np.array_equal(solo, mus[h])
         g64 = gu.gpu_moments(cfg["lattices"][h], refs[h][2], refs[h][3], kpm.F64, M, R, vec, seed, h)
-        gu.assert_fp64(g64, refs[h][1], f"config3 c128 instance {h}")
+        gu.assert_fp64(g64, refs[h][1], f"config3 c128 instance {h} (L={L})")
+    assert any(cfg["lattices"][h].L[0] == 48 for h in checked)
     assert all(np.all(np.isfinite(m)) and abs(m[0] - 1.0) < 1e-6 for m in mus)
     for h in hs:
         h.free()

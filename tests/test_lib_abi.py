@@ -68,6 +68,8 @@ def test_argument_validation_without_device(L):
     h = ctypes.c_void_p()
     assert L.kpm_build(None, 1.0, 0.0, 0, None, ctypes.byref(h)) == 1
     assert L.kpm_workspace_bytes(None, 16, 4, 0) == 0
+    a, b = ctypes.c_double(), ctypes.c_double()
+    assert L.kpm_ham_get_scale(None, ctypes.byref(a), ctypes.byref(b)) == 1
     assert L.kpm_moments(None, 16, 4, 0, 1, 0, None, 0, None, None) != 0
     assert L.kpm_dos(None, 16, 1, 64, 1.0, 0.0, None, None, None) == 1
     assert L.kpm_start_vectors(5, 0, 0, 0, 10, 2, None, None) == 1
@@ -77,7 +79,8 @@ def test_argument_validation_without_device(L):
     assert L.kpm_set_launch(3, 0) == 1
     assert L.kpm_set_launch(4, 4) == 1
     assert L.kpm_set_launch(5, 2) == 1
-    assert L.kpm_set_launch(9, 2) == 1          # passes of 1, 2 or 3 steps only (0, 1, 3)
+    assert L.kpm_set_launch(9, 2) == 1          # depth keys: 0 one step, 1 two, 3..6, -1 default; 2 is none
+    assert L.kpm_set_launch(9, 7) == 1
     assert L.kpm_set_launch(99, 1) == 1
     d = kpm.HamDesc()
     d.kind = 3
