@@ -352,7 +352,7 @@ def pmc_summary(root):
         print(f"{name} grid={grid}: {vals}")
 
 
-def serving_leg(n_requests, logN_max, load, seed=1005, fp64_stable=0.0):
+def serving_leg(n_requests, logN_max, load, seed=1005, fp64_stable=0.0, capacity_only=False):
     """Config-5 recipe (Poisson arrivals; N log-uniform from 2^12 up to 2^logN_max; 2D/3D; real or
     spin hopping; M in {256, 1024, 4096, 8192}; R in [8, 64]).  Capacity of the batched FP32 server
     is measured with every request present at t = 0; a wall-clock trace at each offered load
@@ -389,6 +389,8 @@ def serving_leg(n_requests, logN_max, load, seed=1005, fp64_stable=0.0):
     out = {"requests": n_requests, "logN_range": [12, logN_max],
            "fp32_capacity_req_per_s": capacity, "fp32_throughput_updates_per_s": updates / makespan,
            "fp32_throughput_GBps_algorithmic": alg_bytes / makespan / 1e9, "loads": []}
+    if capacity_only:
+        return out
     for ld in loads:
         arrivals = np.cumsum(gaps / (ld * capacity))
         log(f"bench: load {ld}: trace over {arrivals[-1]:.2f} s")
@@ -618,6 +620,8 @@ def main():
                     help="config5: also serve at this fraction of the FP64 capacity (0: off)")
     ap.add_argument("--serve-load", type=lambda v: [float(x) for x in v.split(",")], default=[0.7],
                     help="offered load(s) as a fraction of the measured FP32 capacity, comma separated")
+    ap.add_argument("--serve-capacity-only", action="store_true",
+                    help="config5: measure the FP32 server's capacity (all requests at t = 0) and stop")
     ap.add_argument("--tpt", type=int, default=0, help="chunks per thread per tile (1, 2, 4)")
     ap.add_argument("--max-blocks", type=int, default=0)
     ap.add_argument("--march", type=int, default=-1, help="1: march kernels for lattices, 0: flat kernels")
@@ -691,7 +695,8 @@ def main():
                    tblock=None if args.tblock < 0 else args.tblock)
     if args.workload == "config5":
         # the serving record alone: FP32 continuous batching vs the plain FP64 FCFS path
-        sv = serving_leg(args.serve_requests, args.serve_logn_max, args.serve_load, fp64_stable=args.serve_fp64_stable)
+        sv = serving_leg(args.serve_requests, args.serve_logn_max, args.serve_load, fp64_stable=args.serve_fp64_stable,
+                         capacity_only=args.serve_capacity_only)
         print(json.dumps({"metric": "p50/p99 solve latency under a Poisson request stream", "unit": "ms",
                           "n_gpus": 1, "data": "synthetic", "higher_is_better": False,
                           "config": {"workload": WORKLOAD_TEXT["config5"]}, "serving": sv}), flush=True)
