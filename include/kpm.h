@@ -215,6 +215,25 @@ kpm_status kpm_moments(kpm_ham *h, int32_t M, int32_t R, int32_t vec, uint64_t s
                        uint64_t instance, void *workspace_dev, size_t ws_bytes,
                        double *mu_dev, void *stream);
 
+/* kpm_moments without a caller workspace and without any allocation, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops or harnesses that forbid hipMalloc).  The workspace is the
+ * library's own static device scratch of KPM_STATIC_SCRATCH_BYTES (64 MiB),
+ * one copy per GPU, held from the library's load until the process ends; the
+ * solve must fit it (kpm_workspace_bytes(h, M, R, vec) <= KPM_STATIC_SCRATCH_BYTES,
+ * else KPM_ERR_WORKSPACE and nothing is enqueued).  The caller still passes the
+ * operator and mu_dev[M].  No hipMalloc, hipFree or other allocating call is
+ * made (the scratch address is looked up once per device, on that device's
+ * first call).  Every call on one GPU shares its scratch and leaves its
+ * contents behind (the solve writes each value before reading it, so nothing
+ * needs clearing): calls that overlap on one GPU (other streams, other host
+ * threads) race and must be serialised by the caller.  Results are bitwise
+ * those of kpm_moments with the same arguments. */
+#define KPM_STATIC_SCRATCH_BYTES (64u << 20)
+size_t kpm_static_scratch_bytes(void);
+kpm_status kpm_moments_static(kpm_ham *h, int32_t M, int32_t R, int32_t vec, uint64_t seed,
+                              uint64_t instance, double *mu_dev, void *stream);
+
 /* The same solve split into chunks, so that a caller can interleave other work
  * (serving) or stop and resume: begin draws r_0 and runs the first product;
  * advance runs up to max_steps further recursion steps and reports how many

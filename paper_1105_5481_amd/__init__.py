@@ -72,6 +72,8 @@ def lib():
         "kpm_ham_get_scale": (i32, [P, P, P]),
         "kpm_workspace_bytes": (sz, [P, i32, i32, i32]),
         "kpm_moments": (i32, [P, i32, i32, i32, u64, u64, P, sz, P, P]),
+        "kpm_moments_static": (i32, [P, i32, i32, i32, u64, u64, P, P]),
+        "kpm_static_scratch_bytes": (sz, []),
         "kpm_solve_begin": (i32, [P, i32, i32, i32, u64, u64, P, sz, P, P]),
         "kpm_solve_advance": (i32, [P, i32, P, P]),
         "kpm_solve_finish": (i32, [P, P, P]),
@@ -333,6 +335,18 @@ def moments(ham: Hamiltonian, M: int, R: int, vec: int = VEC_RADEMACHER, seed: i
     mu = out if out is not None else torch.empty(M, dtype=torch.float64, device=ham.device)
     _check(lib().kpm_moments(ham.handle, M, R, vec, seed, instance, ws.data_ptr(), nb, mu.data_ptr(),
                              _stream(stream)), "kpm_moments")
+    return mu
+
+
+@_stream_scoped
+def moments_static(ham: Hamiltonian, M: int, R: int, vec: int = VEC_RADEMACHER, seed: int = 0, instance: int = 0,
+                   stream=None, out=None):
+    """mu_0..mu_{M-1} like `moments`, run in the library's static device scratch (kpm_moments_static:
+    no device allocation by the library; pass `out` to avoid torch's as well)."""
+    torch = _torch()
+    mu = out if out is not None else torch.empty(M, dtype=torch.float64, device=ham.device)
+    _check(lib().kpm_moments_static(ham.handle, M, R, vec, seed, instance, mu.data_ptr(), _stream(stream)),
+           "kpm_moments_static")
     return mu
 
 

@@ -1189,6 +1189,54 @@ kpm_status kpm_moments(kpm_ham *h, int32_t M, int32_t R, int32_t vec, uint64_t s
 }
 
 // ---------------------------------------------------------------------------
+// the same solve with the library's own device scratch (no allocation)
+// ---------------------------------------------------------------------------
+namespace {
+// One copy per device, held from the code object's load until the process ends.
+__device__ __align__(256) char scratch[KPM_STATIC_SCRATCH_BYTES];
+
+// Device address of this device's copy of `scratch`, looked up once per device with
+// that device current.  In host code the name `scratch` is only a host-side stand-in:
+// kernels and copies must be given this address instead.
+kpm_status scratch_address(void **out)
+{
+    static std::mutex mu;
+    static void *addr[64] = {nullptr};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return KPM_ERR_DEVICE;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            g_last_hip = e != hipSuccess ? e : hipErrorInvalidSymbol;
+            return KPM_ERR_DEVICE;
+        }
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return KPM_OK;
+}
+}  // namespace
+
+size_t kpm_static_scratch_bytes(void) { return (size_t)KPM_STATIC_SCRATCH_BYTES; }
+
+kpm_status kpm_moments_static(kpm_ham *h, int32_t M, int32_t R, int32_t vec, uint64_t seed, uint64_t instance,
+                              double *mu_dev, void *stream)
+{
+    if (!h || !mu_dev) return KPM_ERR_INVALID_ARG;
+    const size_t need = kpm_workspace_bytes(h, M, R, vec);
+    if (need == 0) return KPM_ERR_INVALID_ARG;
+    if (need > (size_t)KPM_STATIC_SCRATCH_BYTES) return KPM_ERR_WORKSPACE;
+    void *ws = nullptr;
+    const kpm_status e = scratch_address(&ws);
+    if (e != KPM_OK) return e;
+    // the solve writes every value of its workspace before reading it, so the
+    // previous call's contents need no clearing
+    return kpm_moments(h, M, R, vec, seed, instance, ws, (size_t)KPM_STATIC_SCRATCH_BYTES, mu_dev, stream);
+}
+
+// ---------------------------------------------------------------------------
 // batched solves
 // ---------------------------------------------------------------------------
 namespace {
