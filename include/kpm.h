@@ -374,10 +374,11 @@ kpm_status kpm_start_vectors(int32_t vec, int32_t complex_layout, uint64_t seed,
  *                                vectors and operators total at most this many MiB (default
  *                                224, so a wave stays in the Infinity Cache); a wave runs all
  *                                its recursion steps before the next starts.  0 = one wave
- *   KPM_LAUNCH_TBLOCK            solves on 2D lattices (real or spin hopping; C chunks per
- *                                site dividing 512, L_x >= 512/C) take several recursion
- *                                steps per pass over the vectors (temporal blocking; 4
- *                                vector buffers instead of 2, bitwise the same vectors):
+ *   KPM_LAUNCH_TBLOCK            solves on 2D lattices (real or spin hopping; C <= 64 chunks
+ *                                per site, windows of floor(512/C) sites, L_x >= 512/C) take
+ *                                several recursion steps per pass over the vectors (temporal
+ *                                blocking; 4 vector buffers instead of 2, bitwise the same
+ *                                vectors; in a dynamic batch they share blocked launches):
  *                                D = 3 .. 6: D steps per pass where at least D remain (only
  *                                r_{n+D-1} and r_{n+D} are written; x-tiles with D-site
  *                                halos, L_y >= 2D), shorter passes for the rest; -1

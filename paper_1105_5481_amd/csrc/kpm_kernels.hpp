@@ -80,6 +80,9 @@ struct Inst {
     const int32_t *col;
     const void *val;   // S[nnz] or S[nnz][2]
     void *buf0, *buf1;
+    void *tb2, *tb3;   // temporal blocking: buffers 2 and 3 of four (buf0, buf1 are 0 and 1)
+    int32_t tbp, tbc;  // ... and which of them hold r_{step0-1}, r_{step0} (batched passes)
+    int32_t tbfull, tbrem;  // batched passes of this chunk: tbfull of depth tbh, then one of depth tbrem
     double *partial;   // [pslots][tiles][4]
     double *dots;      // [K+1][4] = (nn.hi, nn.lo, nm.hi, nm.lo)
     double *mu;        // [M]

@@ -560,9 +560,10 @@ bool make_plan(const kpm_ham *h, int32_t M, int32_t R, int32_t vec, Plan &p, boo
         p.tiles = SMALL_WAVES;   // per-wave dot partials
         p.xcd = 0;
     } else if (allow_tb && g_tblock && g_march && (h->opk == OP_REAL2 || h->opk == OP_SPIN2) &&
-               TB_BLOCK % p.C == 0 && tb_halo(h->prec, h->opk, p.C) >= 2 && h->L[0] >= TB_BLOCK / p.C &&
+               tb_halo(h->prec, h->opk, p.C) >= 2 && h->L[0] >= TB_BLOCK / p.C &&
                h->L[1] >= 2 * tb_halo(h->prec, h->opk, p.C)) {
-        // several steps per pass: x-tiles of TB_BLOCK/C - 2 tbh owned sites, segments of rows
+        // several steps per pass: windows of floor(TB_BLOCK/C) sites (the threads beyond
+        // window * C idle), x-tiles of the window less 2 tbh halo sites, segments of rows
         p.mode = MODE_TB;
         p.nbuf = 4;
         p.tbh = tb_halo(h->prec, h->opk, p.C);
@@ -691,7 +692,7 @@ kpm_status launch_init_tb(int prec, int wide, const Inst *tab, uint32_t blocks, 
 }
 
 // depth-D passes (D = 1 .. 6) of the temporally blocked kernel, real or spin hopping
-typedef void (*tbd_fn)(const Inst *, int32_t, const void *, const void *, void *, void *);
+typedef void (*tbd_fn)(const Inst *, const uint32_t *, int32_t, const void *, const void *, void *, void *);
 template <typename S, int OPK, int D>
 tbd_fn tbd_pick(int wide, int nt)
 {
@@ -705,8 +706,12 @@ tbd_fn tbd_for(int prec, int opk, int wide, int nt)
         return prec == KPM_F64 ? tbd_pick<double, OP_SPIN2, D>(wide, nt) : tbd_pick<float, OP_SPIN2, D>(wide, nt);
     return prec == KPM_F64 ? tbd_pick<double, OP_REAL2, D>(wide, nt) : tbd_pick<float, OP_REAL2, D>(wide, nt);
 }
-kpm_status launch_tbd(int depth, int prec, int opk, int wide, int nt, const Inst *tab, uint32_t blocks, int32_t n,
-                      const void *prev, const void *cur, void *outa, void *outb, hipStream_t st)
+// Solo: tab[0] at step arg with the given buffers (bmap = nullptr).  Batched: the
+// instances of the block map run pass arg of their chunk (arg = -1: their
+// remainder pass of this depth), buffers from the table.
+kpm_status launch_tbd(int depth, int prec, int opk, int wide, int nt, const Inst *tab, const uint32_t *bmap,
+                      uint32_t blocks, int32_t arg, const void *prev, const void *cur, void *outa, void *outb,
+                      hipStream_t st)
 {
     if (opk != OP_REAL2 && opk != OP_SPIN2) return KPM_ERR_INVALID_ARG;
     tbd_fn f = nullptr;
@@ -719,7 +724,7 @@ kpm_status launch_tbd(int depth, int prec, int opk, int wide, int nt, const Inst
     case 6: f = tbd_for<6>(prec, opk, wide, nt); break;
     default: return KPM_ERR_INVALID_ARG;
     }
-    hipLaunchKernelGGL(f, dim3(blocks), dim3(TB_BLOCK), 0, st, tab, n, prev, cur, outa, outb);
+    hipLaunchKernelGGL(f, dim3(blocks), dim3(TB_BLOCK), 0, st, tab, bmap, arg, prev, cur, outa, outb);
     return check_launch();
 }
 
@@ -1069,6 +1074,10 @@ kpm_status kpm_solve_begin(kpm_ham *h, int32_t M, int32_t R, int32_t vec, uint64
         // four vector buffers; r_0 goes to buffer 1 (buffer 0 plays r_{-1}, never read)
         char *b = s->ws + align256(sizeof(Inst)) + p.part_bytes + p.dots_bytes;
         for (int q = 0; q < 4; ++q) s->tbuf[q] = b + (size_t)q * p.buf_bytes;
+        s->inst.buf0 = s->tbuf[0];
+        s->inst.buf1 = s->tbuf[1];
+        s->inst.tb2 = s->tbuf[2];
+        s->inst.tb3 = s->tbuf[3];
         s->tb_prev = 0;
         s->tb_cur = 1;
         if (e == KPM_OK) e = launch_init_tb(h->prec, p.wide, s->tab_dev, p.nb, s->tbuf[1], st);
@@ -1099,6 +1108,29 @@ kpm_status kpm_solve_begin(kpm_ham *h, int32_t M, int32_t R, int32_t vec, uint64
     return KPM_OK;
 }
 
+// Temporal blocking: the two buffers of four not holding (r_{n-1}, r_n), ascending.
+static void tb_free(int prev, int cur, int f[2])
+{
+    int nf = 0;
+    for (int q = 0; q < 4; ++q)
+        if (q != prev && q != cur) f[nf++] = q;
+}
+// Buffer roles after a pass of `depth` steps: depth >= 2 leaves (r_{n+depth-1},
+// r_{n+depth}) in the free buffers (ascending); one step leaves r_{n+1} in the
+// lower free buffer.  The batched kernel derives the same roles in-kernel.
+static void tb_rotate(int &prev, int &cur, int depth)
+{
+    int f[2];
+    tb_free(prev, cur, f);
+    if (depth >= 2) {
+        prev = f[0];
+        cur = f[1];
+    } else {
+        prev = cur;
+        cur = f[0];
+    }
+}
+
 static kpm_status solve_reduce_pending(kpm_solve *s, hipStream_t st)
 {
     const int32_t n = s->written - s->reduced;
@@ -1123,21 +1155,14 @@ kpm_status kpm_solve_advance(kpm_solve *s, int32_t max_steps, void *stream, int3
             const int32_t adv = std::min(std::min(I.K - s->next, max_steps - done), I.tbh);
             if (s->written - s->reduced + adv > I.pslots) e = solve_reduce_pending(s, st);
             if (e != KPM_OK) break;
-            int f[2], nf = 0;
-            for (int q = 0; q < 4; ++q)
-                if (q != s->tb_prev && q != s->tb_cur) f[nf++] = q;
+            int f[2];
+            tb_free(s->tb_prev, s->tb_cur, f);
             // r_{n+adv-1}, r_{n+adv} into the free buffers, which become (prev, cur); a single
             // step writes r_{n+1} alone
-            e = launch_tbd(adv, s->h->prec, s->h->opk, s->wide, I.nt, s->tab_dev, I.nb, s->next,
+            e = launch_tbd(adv, s->h->prec, s->h->opk, s->wide, I.nt, s->tab_dev, nullptr, I.nb, s->next,
                            s->tbuf[s->tb_prev], s->tbuf[s->tb_cur], s->tbuf[adv >= 2 ? f[0] : f[1]],
                            s->tbuf[adv >= 2 ? f[1] : f[0]], st);
-            if (adv >= 2) {
-                s->tb_prev = f[0];
-                s->tb_cur = f[1];
-            } else {
-                s->tb_prev = s->tb_cur;
-                s->tb_cur = f[0];
-            }
+            tb_rotate(s->tb_prev, s->tb_cur, adv);
             s->next += adv;
             s->written += adv;
             done += adv;
@@ -1266,7 +1291,7 @@ uint32_t place_blocks(std::vector<Inst> &ins, std::vector<uint32_t> &map)
         small.clear();
     }
     auto cost = [&](uint32_t r) { return ins[r].nel ? (uint64_t)ins[r].nel : (uint64_t)ins[r].nb; };
-    auto units = [&](uint32_t r) { return ins[r].mode == MODE_MARCH ? ins[r].nct : ins[r].tiles; };
+    auto units = [&](uint32_t r) { return (ins[r].mode == MODE_MARCH || ins[r].mode == MODE_TB) ? ins[r].nct : ins[r].tiles; };
     std::stable_sort(small.begin(), small.end(), [&](uint32_t a, uint32_t b) { return cost(a) > cost(b); });
     uint64_t total = 0;
     for (uint32_t r : small) total += cost(r);
@@ -1602,41 +1627,56 @@ kpm_status kpm_batch_advance(kpm_batch *b, int32_t steps, void *stream)
     // active members grouped by kernel class; the table also carries each
     // member's pending reduction range
     std::vector<kpm_solve *> act;
-    for (kpm_solve *s : b->members) {
-        if (s->inst.mode == MODE_TB) {   // temporally blocked solves advance with their own launches
-            if (s->next < s->inst.K) {
-                if (kpm_status r = kpm_solve_advance(s, steps, stream, nullptr)) return r;
-            }
-            continue;
-        }
+    for (kpm_solve *s : b->members)
         if (s->inst.mode != MODE_SMALL && (s->next < s->inst.K || s->written > s->reduced)) act.push_back(s);
-    }
     if (act.empty() || steps == 0) return KPM_OK;
     // the members of one launch share the caches
     uint64_t state = 0;
     for (kpm_solve *s : act) state += s->state;
     const int nt = stream_choice(state);
+    // one-step members by kernel class; temporally blocked members by (hopping,
+    // addressing, depth of their full passes)
+    auto key_of = [&](const kpm_solve *s) {
+        if (s->inst.mode == MODE_TB) return 1000 + (s->inst.opk * 2 + s->wide) * 8 + s->inst.tbh;
+        return kernel_key(s->inst.opk, s->inst.mode, s->wide, nt);
+    };
     std::vector<int> keys;
     for (kpm_solve *s : act) {
-        const int key = kernel_key(s->inst.opk, s->inst.mode, s->wide, nt);
+        const int key = key_of(s);
         if (std::find(keys.begin(), keys.end(), key) == keys.end()) keys.push_back(key);
     }
     std::vector<Inst> tab;
     std::vector<uint32_t> map;
-    struct Group { int opk, mode, wide, nt; uint32_t first, count, blocks; size_t map_off; };
+    struct Group {
+        int opk, mode, wide, nt;
+        uint32_t first, count, blocks;
+        size_t map_off;
+        int tbh, maxfull;   // blocked groups: depth of the full passes, most full passes of a member
+        uint32_t rems;      // blocked groups: bit r set if a member ends the chunk with a pass of depth r
+    };
     std::vector<Group> groups;
     int32_t max_red = 0;
     for (int key : keys) {
-        Group g{0, 0, 0, 0, (uint32_t)tab.size(), 0, 0, map.size()};
+        Group g{0, 0, 0, 0, (uint32_t)tab.size(), 0, 0, map.size(), 0, 0, 0u};
         std::vector<Inst> ins;
         for (kpm_solve *s : act) {
-            if (kernel_key(s->inst.opk, s->inst.mode, s->wide, nt) != key) continue;
+            if (key_of(s) != key) continue;
             Inst I = s->inst;
             I.nt = nt;
             I.step0 = s->next;
             I.red_lo = s->reduced;
             I.red_n = s->written - s->reduced;
             max_red = std::max(max_red, I.red_n);
+            if (I.mode == MODE_TB) {
+                const int32_t adv = std::min(steps, I.K - s->next);
+                I.tbfull = adv / I.tbh;
+                I.tbrem = adv % I.tbh;
+                I.tbp = s->tb_prev;
+                I.tbc = s->tb_cur;
+                g.tbh = I.tbh;
+                g.maxfull = std::max(g.maxfull, I.tbfull);
+                if (I.tbrem) g.rems |= 1u << I.tbrem;
+            }
             g.opk = I.opk;
             g.mode = I.mode;
             g.wide = s->wide;
@@ -1658,15 +1698,31 @@ kpm_status kpm_batch_advance(kpm_batch *b, int32_t steps, void *stream)
         e = check_launch();
     }
     const int prec = act[0]->h->prec;
+    // step k of the one-step members; the blocked members' full passes start at
+    // the steps k = j * tbh, their last, shorter passes follow the loop
     for (int32_t k = 0; k < steps && e == KPM_OK; ++k)
-        for (const Group &g : groups)
-            if (e == KPM_OK)
+        for (const Group &g : groups) {
+            if (e != KPM_OK) break;
+            if (g.mode != MODE_TB)
                 e = launch_step(prec, g.opk, g.mode, g.wide, g.nt, tab_dev + g.first, map_dev + g.map_off, g.blocks, k,
                                 st);
+            else if (k % g.tbh == 0 && k / g.tbh < g.maxfull)
+                e = launch_tbd(g.tbh, prec, g.opk, g.wide, g.nt, tab_dev + g.first, map_dev + g.map_off, g.blocks,
+                               k / g.tbh, nullptr, nullptr, nullptr, nullptr, st);
+        }
+    for (const Group &g : groups)
+        for (int r = 1; r < 7 && e == KPM_OK; ++r)
+            if (g.mode == MODE_TB && (g.rems >> r & 1u))
+                e = launch_tbd(r, prec, g.opk, g.wide, g.nt, tab_dev + g.first, map_dev + g.map_off, g.blocks, -1,
+                               nullptr, nullptr, nullptr, nullptr, st);
     if (e != KPM_OK) return e;
     for (kpm_solve *s : act) {
         s->reduced = s->written;
         const int32_t done = std::min(steps, s->inst.K - s->next);
+        if (s->inst.mode == MODE_TB) {
+            for (int32_t j = 0; j < done / s->inst.tbh; ++j) tb_rotate(s->tb_prev, s->tb_cur, s->inst.tbh);
+            if (done % s->inst.tbh) tb_rotate(s->tb_prev, s->tb_cur, done % s->inst.tbh);
+        }
         s->next += done;
         s->written += done;
     }

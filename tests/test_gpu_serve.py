@@ -26,6 +26,13 @@ def _requests():
         (wl.Lattice(dim=2, L=(50, 60, 1), t=1.0, hop=wl.HOP_SPIN,
                     spinor=wl.spinor_of(*wl.spins_uniform(3000, 7))), 150, 5, wl.VEC_PHASE, 6),
         (wl.square_lattice(128, W=0.5, seed=8), 512, 4, wl.VEC_RADEMACHER, 9),
+        # temporally blocked 2D solves (4-step and 3-step passes, chunk remainders)
+        (wl.Lattice(dim=2, L=(300, 40, 1), t=1.0, onsite=wl.anderson_onsite(12000, 2.0, 9)), 270, 8,
+         wl.VEC_RADEMACHER, 1),
+        (wl.Lattice(dim=2, L=(200, 30, 1), t=1.0, hop=wl.HOP_SPIN,
+                    spinor=wl.spinor_of(*wl.spins_uniform(6000, 10))), 180, 6, wl.VEC_PHASE, 2),
+        (wl.Lattice(dim=2, L=(260, 20, 1), t=1.0, onsite=wl.anderson_onsite(5200, 1.0, 11)), 77, 36,
+         wl.VEC_RADEMACHER, 5),
     ]
     for k, (op, M, R, vec, arr) in enumerate(specs):
         reqs.append(KPMRequest(op=op, M=M, R=R, vec=vec, seed=100 + k, instance=k, arrival=arr, rid=k))
@@ -45,6 +52,13 @@ def test_served_equals_solo_and_overlaps():
     res = srv.run(reqs, clock="chunks")
     srv.close()
     assert [r.status for r in res] == ["ok"] * len(reqs)
+    # the last three run temporally blocked passes inside the shared launches
+    for req in reqs[-3:]:
+        h = kpm.Hamiltonian(req.op, 4.5, 0.0, kpm.F32)
+        s = kpm.Solve(h, req.M, req.R, req.vec, 1, 0)
+        assert kpm.lib().kpm_solve_mode(s._s) == 3
+        s.close()
+        h.free()
     for req, r in zip(reqs, res):
         solo = _solo(req, kpm.F32, r.a, r.b)
         assert np.array_equal(r.mu, solo), req.rid

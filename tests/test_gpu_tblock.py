@@ -23,6 +23,8 @@ CASES = [  # (Lx, Ly, W, R, prec, M): C = 4, 1, 16, 16 chunks per site -> window
     (200, 30, 1.0, 8, kpm.F64, 5),     # a pair and a single step
     (200, 30, 1.0, 8, kpm.F64, 7),     # one triple (three-step passes)
     (200, 30, 1.0, 8, kpm.F32, 9),     # a triple and a single step
+    (260, 20, 1.0, 36, kpm.F32, 50),   # C = 9: a window of 56 sites, 8 of 512 threads idle
+    (260, 20, 1.0, 36, kpm.F64, 37),   # C = 18: a window of 28 sites, depth capped at 7
 ]
 DEPTHS = [1, 3, 4, 5, 6]   # KPM_LAUNCH_TBLOCK: steps per pass (1 means two)
 
@@ -45,6 +47,8 @@ SPIN_CASES = [  # (Lx, Ly, W, R, prec, M, vector kind, spin hopping): chunks per
     (40, 12, 0.5, 128, kpm.F32, 13, wl.VEC_PHASE, True),     # C = 64: depth capped at 2
     (300, 18, 1.0, 3, kpm.F32, 26, wl.VEC_RADEMACHER, True),  # C = 2: real vectors, complex operator
     (150, 20, 1.0, 8, kpm.F64, 30, wl.VEC_PHASE, False),     # C = 8: real hopping, complex vectors
+    (200, 24, 1.0, 20, kpm.F32, 33, wl.VEC_PHASE, True),     # C = 10: a window of 51 sites
+    (200, 24, 0.5, 5, kpm.F64, 29, wl.VEC_PHASE, True),      # C = 5: a window of 102 sites
 ]
 
 
@@ -188,3 +192,52 @@ def test_tblock_default_by_precision_and_hopping(prec, spin, expect):
         s.close()
         h.free()
     assert (mode == 3) == expect
+
+
+@pytest.mark.parametrize("tb", [-1, 1, 3, 6])
+@pytest.mark.parametrize("chunks", [[16], [5, 7, 64], [3, 1, 2, 9]])
+def test_tblock_batched_passes_equal_solo(chunks, tb):
+    """Temporally blocked solves of different depths, step counts and buffer states share the
+    blocked launches of a dynamic batch (a one-step solve beside them): every result equals the
+    same solve run alone, bitwise, and the FP64 ones match the oracle."""
+    specs = [  # (operator, precision, M, R, vector kind): remainders 0..depth-1 over the chunks
+        (_lat(300, 40, 1.0, 21), kpm.F64, 41, 8, wl.VEC_RADEMACHER),
+        (_lat(260, 20, 2.0, 22), kpm.F64, 30, 36, wl.VEC_RADEMACHER),
+        (_spin_lat(200, 24, 1.0, 23), kpm.F64, 27, 4, wl.VEC_PHASE),
+        (_lat(300, 40, 0.5, 24), kpm.F64, 64, 8, wl.VEC_PHASE),
+        (wl.spin_cubic_lattice(12, seed=25), kpm.F64, 33, 3, wl.VEC_PHASE),
+    ]
+    with kpm.launch_settings(small=0, tblock=tb):
+        hs, ss, modes = [], [], []
+        for k, (op, prec, M, R, vec) in enumerate(specs):
+            lo, hi = gu.oracle_bounds(op)
+            a, b = oracle.scale_from_bounds(lo, hi, 0.01)
+            h = kpm.Hamiltonian(op, a, b, prec)
+            hs.append(h)
+            s = kpm.Solve(h, M, R, vec, 30 + k, k)
+            modes.append(kpm.lib().kpm_solve_mode(s._s))
+            ss.append(s)
+        assert modes[:4] == [3, 3, 3, 3] and modes[4] != 3
+        # one solve joins late, after the others have advanced
+        batch = kpm.Batch(capacity=8)
+        for s in ss[:-1]:
+            batch.add(s)
+        q = 0
+        while any(s.remaining > 0 for s in ss):
+            batch.advance(chunks[q % len(chunks)])
+            q += 1
+            if q == 1:
+                batch.add(ss[-1])
+        outs = []
+        for s in ss:
+            batch.remove(s)
+            outs.append(s.finish().cpu().numpy())
+            s.close()
+        batch.free()
+        solo = [kpm.moments(h, M, R, vec, 30 + k, k).cpu().numpy() for k, (h, (_, _, M, R, vec)) in
+                enumerate(zip(hs, specs))]
+    for k, ((op, prec, M, R, vec), h, mu, one) in enumerate(zip(specs, hs, outs, solo)):
+        assert np.array_equal(mu, one), (k, float(np.abs(mu - one).max()))
+        ref = gu.oracle_moments(op, h.a, h.b, M, R, vec, 30 + k, k)
+        gu.assert_fp64(mu, ref, f"batched blocked solve {k}")
+        h.free()
