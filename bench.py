@@ -43,6 +43,7 @@ WORKLOAD_TEXT = {
 CONFIG3_KERNEL = "k_step_march<float, OP_SPIN3> (multi-instance)"
 TB_KERNEL = {d: "k_step_tbd<float, OP_REAL2, %d> (%d step%s per launch)" % (d, d, "s" if d > 1 else "")
              for d in range(1, 7)}
+TB3_KERNEL = "k_step_tb3<float, OP_SPIN3, 2> (2 steps per launch)"
 
 
 def tb_depth(tblock, prec, C=16, spin=False):
@@ -456,11 +457,12 @@ def cpu_baseline(lat, a, b, vec, seed):
 
 
 
-def tb_pass_bytes(N, R, cplx, esz, has_diag, depth):
+def tb_pass_bytes(N, R, cplx, esz, has_diag, depth, bonds_per_site=0):
     """Bytes one temporally blocked pass of `depth` >= 2 steps must move at least: read r_{n-1}
-    and r_n, write r_{n+depth-1} and r_{n+depth} (4 N R e), plus the diagonal once per step."""
+    and r_n, write r_{n+depth-1} and r_{n+depth} (4 N R e), plus the operator (diagonal and
+    forward bonds) once per step."""
     e = esz * (2 if cplx else 1)
-    return 4 * N * R * e + depth * N * (esz if has_diag else 0)
+    return 4 * N * R * e + depth * N * ((esz if has_diag else 0) + bonds_per_site * 2 * esz)
 
 
 def bench_lattice(args, workload, steps, warmup, fp64=True, cpu=True):
@@ -536,9 +538,12 @@ def bench_lattice(args, workload, steps, warmup, fp64=True, cpu=True):
     ms_per_step = dt32 / steps * 1e3
     updates = float(N) * M * R
     value = updates / (dt32 / steps)
-    tblocked = solve_mode.get(kpm.F32) == 3
+    tblocked = solve_mode.get(kpm.F32) in (3, 4)     # 2D blocked passes (3), 3D two-step passes (4)
     chunks = -(-R * (2 if cplx else 1) // 4)  # 16-byte chunks per site (FP32)
-    depth = tb_depth(kpm.get_launch()["tblock"], kpm.F32, chunks) if tblocked else 1   # recursion steps per launch
+    if solve_mode.get(kpm.F32) == 4:
+        depth = 2
+    else:
+        depth = tb_depth(kpm.get_launch()["tblock"], kpm.F32, chunks, lat.hop == wl.HOP_SPIN) if tblocked else 1
     nrec = K if tblocked else K - 1          # begin runs step 0 except with temporal blocking
     step_us = rec32 * 1e3 / nrec             # per recursion step
     launch_us = step_us * depth
@@ -546,7 +551,7 @@ def bench_lattice(args, workload, steps, warmup, fp64=True, cpu=True):
     mode = "march" if kpm.get_launch()["march"] else "flat"
     kernel_name = "k_step_%s<float, %s>" % (mode, "OP_SPIN3" if bonds else "OP_REAL2")
     if tblocked:
-        kernel_name = TB_KERNEL[depth]
+        kernel_name = TB3_KERNEL if solve_mode.get(kpm.F32) == 4 else TB_KERNEL[depth]
     has_diag = s32[0].b != 0.0 or lat.onsite is not None
     bytes_step = algorithmic_bytes_per_step(N, R, cplx, 4, has_diag, bonds)   # the method's 3 streams
     traffic_step = measured_traffic(workload, kernel_name)
@@ -554,7 +559,7 @@ def bench_lattice(args, workload, steps, warmup, fp64=True, cpu=True):
         # the blocked pass moves 4 vector streams for `depth` steps, plus the halo re-reads of its
         # tiles; its rate against the HBM peak is counted from the bytes it moves (rocprof counters
         # of the same kernel source), or, without a current counter record, from its minimum
-        min_launch = tb_pass_bytes(N, R, cplx, 4, has_diag, depth)
+        min_launch = tb_pass_bytes(N, R, cplx, 4, has_diag, depth, bonds)
         moved_launch = traffic_step * depth if traffic_step else min_launch
         achieved = moved_launch / (launch_us * 1e-6) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -653,7 +658,8 @@ def main():
     if args.record_traffic:
         import paper_1105_5481_amd.workloads as wl
         cfg = getattr(wl, args.workload)()
-        kern = {"config2": "k_step_march<float, OP_SPIN3>", "config3": CONFIG3_KERNEL,
+        kern = {"config2": TB3_KERNEL if kpm_default_tblock() != 0 else "k_step_march<float, OP_SPIN3>",
+                "config3": CONFIG3_KERNEL,
                 "config4": TB_KERNEL[tb_depth(kpm_default_tblock(), 1)]}[args.workload]
         extra = {"config2": "--no-fp64 --no-cpu-baseline --no-serve ", "config4": "--no-fp64 --no-cpu-baseline --no-serve --no-secondary ",
                  "config3": ""}[args.workload]

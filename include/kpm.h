@@ -388,6 +388,13 @@ kpm_status kpm_start_vectors(int32_t vec, int32_t complex_layout, uint64_t seed,
  *                                below 2 the solve takes one step per pass.  Batched
  *                                solves (kpm_moments_batched) always take one step per
  *                                pass
+ *   KPM_LAUNCH_TB3               solves on 3D lattices (KPM_LAUNCH_TBLOCK not 0) take two
+ *                                recursion steps per pass (chunk-major vectors, row tiles
+ *                                of whole planes, 4 vector buffers, bitwise the same
+ *                                vectors; solo and dynamic batches): 1 for every 3D
+ *                                lattice, -1 (default) for FP32 recursions with real
+ *                                hopping only, 0 never.  Needs L_x L_y <= 1024 sites or
+ *                                L_x <= 170
  * The partial sums of the dot products are formed per work item, so the
  * moments do not depend on the grid (MAX_BLOCKS) nor on the batch an instance
  * runs in; the other keys change the work items and with them the order in
@@ -403,7 +410,8 @@ typedef enum {
     KPM_LAUNCH_SMALL = 6,
     KPM_LAUNCH_STREAMING = 7,
     KPM_LAUNCH_WAVE_MIB = 8,
-    KPM_LAUNCH_TBLOCK = 9
+    KPM_LAUNCH_TBLOCK = 9,
+    KPM_LAUNCH_TB3 = 10
 } kpm_launch_key;
 kpm_status kpm_set_launch(int32_t key, int32_t value);
 kpm_status kpm_get_launch(int32_t key, int32_t *value);

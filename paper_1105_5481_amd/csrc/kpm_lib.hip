@@ -14,6 +14,7 @@
 #include "kpm_lanczos.hpp"
 #include "kpm_dense.hpp"
 #include "kpm_tblock.hpp"
+#include "kpm_tblock3.hpp"
 
 using namespace kpm;
 
@@ -29,6 +30,7 @@ int g_alternate = 1;                    // march: odd segments walk downwards
 int g_small = 1;                        // solves whose two vector blocks fit in LDS run in one workgroup
 int g_streaming = 2;                    // march: 0 cached, 1 non-temporal access of r_{n-1}/r_{n+1}, 2 by size
 int g_wave_mib = 224;                   // batched solves: vectors + operators per wave (MiB), 0 = one wave
+int g_tb3 = -1;                         // 3D lattices: two steps per pass: 0 off, 1 on, -1 FP32 real hopping only
 int g_tblock = -1;                      // 2D lattices: steps per pass (temporal blocking): 0 one, 1 two, 3..6,
                                         // -1 by precision and hopping (tb_depth)
 // Up to this much state (vectors + operator) r_{n+1} is stored cached, to be read back as r_n
@@ -534,6 +536,36 @@ int stream_choice(uint64_t state_bytes)
     return g_streaming == 2 ? (state_bytes > CACHE_RESIDENT_BYTES ? 1 : 0) : g_streaming;
 }
 
+// Tiling of a 3D lattice for two-step passes (chunk-major vectors): row tiles
+// of T owned rows plus two rows of r_n each side (or the whole plane), at most
+// TB3_TILE elements; segments of at least 4 planes, as many as keep the work
+// items within one block per compute unit (TB3_ITEMS).  False when a row tile
+// cannot hold two owned rows.
+constexpr uint32_t TB3_ITEMS = 512;
+bool tb3_plan(const kpm_ham *h, Plan &p)
+{
+    const uint32_t Lx = (uint32_t)h->L[0], Ly = (uint32_t)h->L[1], Lz = (uint32_t)h->L[2];
+    uint32_t nty = 1, Ty = Ly;
+    if ((uint64_t)Lx * Ly > TB3_TILE) {
+        if (TB3_TILE / Lx < 6) return false;
+        const uint32_t rmax = TB3_TILE / Lx - 4;
+        nty = (Ly + rmax - 1) / rmax;
+        Ty = (Ly + nty - 1) / nty;
+    }
+    const uint64_t units = (uint64_t)p.C * nty;
+    uint32_t nseg = (uint32_t)std::max<uint64_t>(1, TB3_ITEMS / units);
+    nseg = std::max<uint32_t>(1, std::min<uint32_t>(nseg, std::max<uint32_t>(1, Lz / 4)));
+    p.S = (Lz + nseg - 1) / nseg;
+    p.nseg = (Lz + p.S - 1) / p.S;
+    p.P = Ty;
+    p.nct = nty;
+    p.Lm = Lz;
+    p.tiles = (uint32_t)(units * p.nseg);
+    // all chunks of a segment on one XCD (they share its bonds and diagonal in L2)
+    p.xcd = p.nseg >= 8 ? 2 : 0;
+    return true;
+}
+
 bool make_plan(const kpm_ham *h, int32_t M, int32_t R, int32_t vec, Plan &p, bool allow_tb = true)
 {
     if (!h || M < 1 || R < 1 || vec < 0 || vec > 2) return false;
@@ -581,6 +613,13 @@ bool make_plan(const kpm_ham *h, int32_t M, int32_t R, int32_t vec, Plan &p, boo
         p.nseg = (p.Lm + p.S - 1) / p.S;
         p.tiles = p.nct * p.nseg;
         p.xcd = p.nct >= 8 ? 1 : 0;
+    } else if (allow_tb && g_tblock && g_march &&
+               (g_tb3 > 0 ? (h->opk == OP_REAL3 || h->opk == OP_SPIN3)
+                          : (g_tb3 < 0 && h->opk == OP_REAL3 && h->prec == KPM_F32)) &&
+               tb3_plan(h, p)) {
+        p.mode = MODE_TB3;
+        p.nbuf = 4;
+        p.tbh = 2;
     } else if (h->dim && g_march) {
         p.mode = MODE_MARCH;
         p.P = (uint32_t)(h->dim == 3 ? h->L[0] * h->L[1] : h->L[0]);
@@ -691,6 +730,45 @@ kpm_status launch_init_tb(int prec, int wide, const Inst *tab, uint32_t blocks, 
     return check_launch();
 }
 
+kpm_status launch_init_tb3(int prec, int wide, const Inst *tab, uint32_t blocks, void *cur, hipStream_t st)
+{
+    typedef void (*fn)(const Inst *, void *);
+    static const fn fns[2][2] = {{k_init_tb3<double, false>, k_init_tb3<double, true>},
+                                 {k_init_tb3<float, false>, k_init_tb3<float, true>}};
+    hipLaunchKernelGGL(fns[prec == KPM_F64 ? 0 : 1][wide ? 1 : 0], dim3(blocks), dim3(TB3_BLOCK), 0, st, tab, cur);
+    return check_launch();
+}
+
+// one- and two-step passes of the 3D blocked kernel (solo: tab[0] at step arg with
+// the given buffers; batched: pass arg of the block map's instances, -1 = remainder)
+typedef void (*tb3_fn)(const Inst *, const uint32_t *, int32_t, const void *, const void *, void *, void *);
+template <typename S, int OPK, int D>
+tb3_fn tb3_pick(int wide, int nt)
+{
+    return wide ? (nt ? k_step_tb3<S, OPK, true, true, D> : k_step_tb3<S, OPK, true, false, D>)
+                : (nt ? k_step_tb3<S, OPK, false, true, D> : k_step_tb3<S, OPK, false, false, D>);
+}
+template <int D>
+tb3_fn tb3_for(int prec, int opk, int wide, int nt)
+{
+    if (opk == OP_SPIN3)
+        return prec == KPM_F64 ? tb3_pick<double, OP_SPIN3, D>(wide, nt) : tb3_pick<float, OP_SPIN3, D>(wide, nt);
+    return prec == KPM_F64 ? tb3_pick<double, OP_REAL3, D>(wide, nt) : tb3_pick<float, OP_REAL3, D>(wide, nt);
+}
+kpm_status launch_tb3(int depth, int prec, int opk, int wide, int nt, const Inst *tab, const uint32_t *bmap,
+                      uint32_t blocks, int32_t arg, const void *prev, const void *cur, void *outa, void *outb,
+                      hipStream_t st)
+{
+    if ((opk != OP_REAL3 && opk != OP_SPIN3) || depth < 1 || depth > 2) return KPM_ERR_INVALID_ARG;
+    tb3_fn f = depth == 2 ? tb3_for<2>(prec, opk, wide, nt) : tb3_for<1>(prec, opk, wide, nt);
+    hipLaunchKernelGGL(f, dim3(blocks), dim3(TB3_BLOCK), 0, st, tab, bmap, arg, prev, cur, outa, outb);
+    return check_launch();
+}
+// A pass of a blocked solve of either kind.
+kpm_status launch_pass(int mode, int depth, int prec, int opk, int wide, int nt, const Inst *tab, const uint32_t *bmap,
+                       uint32_t blocks, int32_t arg, const void *prev, const void *cur, void *outa, void *outb,
+                       hipStream_t st);
+
 // depth-D passes (D = 1 .. 6) of the temporally blocked kernel, real or spin hopping
 typedef void (*tbd_fn)(const Inst *, const uint32_t *, int32_t, const void *, const void *, void *, void *);
 template <typename S, int OPK, int D>
@@ -726,6 +804,14 @@ kpm_status launch_tbd(int depth, int prec, int opk, int wide, int nt, const Inst
     }
     hipLaunchKernelGGL(f, dim3(blocks), dim3(TB_BLOCK), 0, st, tab, bmap, arg, prev, cur, outa, outb);
     return check_launch();
+}
+
+kpm_status launch_pass(int mode, int depth, int prec, int opk, int wide, int nt, const Inst *tab, const uint32_t *bmap,
+                       uint32_t blocks, int32_t arg, const void *prev, const void *cur, void *outa, void *outb,
+                       hipStream_t st)
+{
+    if (mode == MODE_TB3) return launch_tb3(depth, prec, opk, wide, nt, tab, bmap, blocks, arg, prev, cur, outa, outb, st);
+    return launch_tbd(depth, prec, opk, wide, nt, tab, bmap, blocks, arg, prev, cur, outa, outb, st);
 }
 
 kpm_status launch_init(int prec, int wide, const Inst *tab, const uint32_t *bmap, uint32_t blocks, hipStream_t st)
@@ -1070,7 +1156,7 @@ kpm_status kpm_solve_begin(kpm_ham *h, int32_t M, int32_t R, int32_t vec, uint64
         *out = s;
         return KPM_OK;
     }
-    if (p.mode == MODE_TB) {
+    if (p.mode == MODE_TB || p.mode == MODE_TB3) {
         // four vector buffers; r_0 goes to buffer 1 (buffer 0 plays r_{-1}, never read)
         char *b = s->ws + align256(sizeof(Inst)) + p.part_bytes + p.dots_bytes;
         for (int q = 0; q < 4; ++q) s->tbuf[q] = b + (size_t)q * p.buf_bytes;
@@ -1080,7 +1166,9 @@ kpm_status kpm_solve_begin(kpm_ham *h, int32_t M, int32_t R, int32_t vec, uint64
         s->inst.tb3 = s->tbuf[3];
         s->tb_prev = 0;
         s->tb_cur = 1;
-        if (e == KPM_OK) e = launch_init_tb(h->prec, p.wide, s->tab_dev, p.nb, s->tbuf[1], st);
+        if (e == KPM_OK)
+            e = p.mode == MODE_TB3 ? launch_init_tb3(h->prec, p.wide, s->tab_dev, p.nb, s->tbuf[1], st)
+                                   : launch_init_tb(h->prec, p.wide, s->tab_dev, p.nb, s->tbuf[1], st);
         s->written = 1;
         s->reduced = 0;
         s->next = 0;
@@ -1147,7 +1235,7 @@ kpm_status kpm_solve_advance(kpm_solve *s, int32_t max_steps, void *stream, int3
     hipStream_t st = S(stream);
     const Inst &I = s->inst;
     kpm_status e = KPM_OK;
-    if (I.mode == MODE_TB) {
+    if (I.mode == MODE_TB || I.mode == MODE_TB3) {
         // passes of tbh steps (the tiles' halo); a shorter one for the remainder or a
         // smaller budget
         int32_t done = 0;
@@ -1159,9 +1247,9 @@ kpm_status kpm_solve_advance(kpm_solve *s, int32_t max_steps, void *stream, int3
             tb_free(s->tb_prev, s->tb_cur, f);
             // r_{n+adv-1}, r_{n+adv} into the free buffers, which become (prev, cur); a single
             // step writes r_{n+1} alone
-            e = launch_tbd(adv, s->h->prec, s->h->opk, s->wide, I.nt, s->tab_dev, nullptr, I.nb, s->next,
-                           s->tbuf[s->tb_prev], s->tbuf[s->tb_cur], s->tbuf[adv >= 2 ? f[0] : f[1]],
-                           s->tbuf[adv >= 2 ? f[1] : f[0]], st);
+            e = launch_pass(I.mode, adv, s->h->prec, s->h->opk, s->wide, I.nt, s->tab_dev, nullptr, I.nb, s->next,
+                            s->tbuf[s->tb_prev], s->tbuf[s->tb_cur], s->tbuf[adv >= 2 ? f[0] : f[1]],
+                            s->tbuf[adv >= 2 ? f[1] : f[0]], st);
             tb_rotate(s->tb_prev, s->tb_cur, adv);
             s->next += adv;
             s->written += adv;
@@ -1291,7 +1379,10 @@ uint32_t place_blocks(std::vector<Inst> &ins, std::vector<uint32_t> &map)
         small.clear();
     }
     auto cost = [&](uint32_t r) { return ins[r].nel ? (uint64_t)ins[r].nel : (uint64_t)ins[r].nb; };
-    auto units = [&](uint32_t r) { return (ins[r].mode == MODE_MARCH || ins[r].mode == MODE_TB) ? ins[r].nct : ins[r].tiles; };
+    auto units = [&](uint32_t r) {
+        if (ins[r].mode == MODE_TB3) return ins[r].nct * ins[r].C;
+        return (ins[r].mode == MODE_MARCH || ins[r].mode == MODE_TB) ? ins[r].nct : ins[r].tiles;
+    };
     std::stable_sort(small.begin(), small.end(), [&](uint32_t a, uint32_t b) { return cost(a) > cost(b); });
     uint64_t total = 0;
     for (uint32_t r : small) total += cost(r);
@@ -1638,6 +1729,7 @@ kpm_status kpm_batch_advance(kpm_batch *b, int32_t steps, void *stream)
     // addressing, depth of their full passes)
     auto key_of = [&](const kpm_solve *s) {
         if (s->inst.mode == MODE_TB) return 1000 + (s->inst.opk * 2 + s->wide) * 8 + s->inst.tbh;
+        if (s->inst.mode == MODE_TB3) return 2000 + s->inst.opk * 2 + s->wide;
         return kernel_key(s->inst.opk, s->inst.mode, s->wide, nt);
     };
     std::vector<int> keys;
@@ -1667,7 +1759,7 @@ kpm_status kpm_batch_advance(kpm_batch *b, int32_t steps, void *stream)
             I.red_lo = s->reduced;
             I.red_n = s->written - s->reduced;
             max_red = std::max(max_red, I.red_n);
-            if (I.mode == MODE_TB) {
+            if (I.mode == MODE_TB || I.mode == MODE_TB3) {
                 const int32_t adv = std::min(steps, I.K - s->next);
                 I.tbfull = adv / I.tbh;
                 I.tbrem = adv % I.tbh;
@@ -1703,23 +1795,23 @@ kpm_status kpm_batch_advance(kpm_batch *b, int32_t steps, void *stream)
     for (int32_t k = 0; k < steps && e == KPM_OK; ++k)
         for (const Group &g : groups) {
             if (e != KPM_OK) break;
-            if (g.mode != MODE_TB)
+            if (g.mode != MODE_TB && g.mode != MODE_TB3)
                 e = launch_step(prec, g.opk, g.mode, g.wide, g.nt, tab_dev + g.first, map_dev + g.map_off, g.blocks, k,
                                 st);
             else if (k % g.tbh == 0 && k / g.tbh < g.maxfull)
-                e = launch_tbd(g.tbh, prec, g.opk, g.wide, g.nt, tab_dev + g.first, map_dev + g.map_off, g.blocks,
-                               k / g.tbh, nullptr, nullptr, nullptr, nullptr, st);
+                e = launch_pass(g.mode, g.tbh, prec, g.opk, g.wide, g.nt, tab_dev + g.first, map_dev + g.map_off,
+                                g.blocks, k / g.tbh, nullptr, nullptr, nullptr, nullptr, st);
         }
     for (const Group &g : groups)
         for (int r = 1; r < 7 && e == KPM_OK; ++r)
-            if (g.mode == MODE_TB && (g.rems >> r & 1u))
-                e = launch_tbd(r, prec, g.opk, g.wide, g.nt, tab_dev + g.first, map_dev + g.map_off, g.blocks, -1,
-                               nullptr, nullptr, nullptr, nullptr, st);
+            if ((g.mode == MODE_TB || g.mode == MODE_TB3) && (g.rems >> r & 1u))
+                e = launch_pass(g.mode, r, prec, g.opk, g.wide, g.nt, tab_dev + g.first, map_dev + g.map_off, g.blocks,
+                                -1, nullptr, nullptr, nullptr, nullptr, st);
     if (e != KPM_OK) return e;
     for (kpm_solve *s : act) {
         s->reduced = s->written;
         const int32_t done = std::min(steps, s->inst.K - s->next);
-        if (s->inst.mode == MODE_TB) {
+        if (s->inst.mode == MODE_TB || s->inst.mode == MODE_TB3) {
             for (int32_t j = 0; j < done / s->inst.tbh; ++j) tb_rotate(s->tb_prev, s->tb_cur, s->inst.tbh);
             if (done % s->inst.tbh) tb_rotate(s->tb_prev, s->tb_cur, done % s->inst.tbh);
         }
@@ -2097,6 +2189,10 @@ kpm_status kpm_set_launch(int32_t key, int32_t value)
         if (value < -1 || value == 2 || value > 6) return KPM_ERR_INVALID_ARG;
         g_tblock = value;
         return KPM_OK;
+    case KPM_LAUNCH_TB3:
+        if (value < -1 || value > 1) return KPM_ERR_INVALID_ARG;
+        g_tb3 = value;
+        return KPM_OK;
     }
     return KPM_ERR_INVALID_ARG;
 }
@@ -2115,6 +2211,7 @@ kpm_status kpm_get_launch(int32_t key, int32_t *value)
     case KPM_LAUNCH_STREAMING: *value = g_streaming; return KPM_OK;
     case KPM_LAUNCH_WAVE_MIB: *value = g_wave_mib; return KPM_OK;
     case KPM_LAUNCH_TBLOCK: *value = g_tblock; return KPM_OK;
+    case KPM_LAUNCH_TB3: *value = g_tb3; return KPM_OK;
     }
     return KPM_ERR_INVALID_ARG;
 }

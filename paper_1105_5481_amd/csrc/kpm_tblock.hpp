@@ -20,6 +20,46 @@ constexpr int MODE_TB = 3;   // plan mode of solves run by these kernels
 // are held to 128 VGPRs (4 waves per SIMD), so that the second block fits.
 #define TB_WAVES_PER_EU(S, D) ((sizeof(S) == 4 ? (D) <= 4 : (D) <= 3) ? 4 : 1)
 
+// Batched passes: the pass a launch with argument `arg` runs for instance I
+// (arg >= 0: full-depth pass arg of the chunk, D = tbh; arg < 0: the remainder
+// pass, D = tbrem), its first step n and its buffer roles.  Pass j starts at
+// step step0 + j * tbh; a pass of depth >= 2 writes its two outputs to the two
+// buffers not holding (r_{n-1}, r_n), in ascending order, so pass j reads the
+// chunk's starting pair (tbp, tbc) itself (j = 0), its complement (j odd) or
+// the pair in ascending order (j even >= 2).  False if I has no such pass.
+__device__ __forceinline__ bool tb_pass_roles(const Inst &I, int32_t arg, int D, int32_t &n, const void *&prev,
+                                              const void *&cur, void *&outa, void *&outb)
+{
+    int32_t j = arg;
+    if (arg < 0) {
+        if (I.tbrem != D) return false;
+        j = I.tbfull;
+    } else if (j >= I.tbfull) {
+        return false;
+    }
+    n = I.step0 + j * I.tbh;
+    void *const bufs[4] = {I.buf0, I.buf1, I.tb2, I.tb3};
+    int p = I.tbp, c = I.tbc;
+    if (j > 0) {
+        const int lo = min(p, c), hi = max(p, c);
+        int f0 = 0;
+        while (f0 == lo || f0 == hi) ++f0;
+        int f1 = f0 + 1;
+        while (f1 == lo || f1 == hi) ++f1;
+        p = (j & 1) ? f0 : lo;
+        c = (j & 1) ? f1 : hi;
+    }
+    int f0 = 0;
+    while (f0 == p || f0 == c) ++f0;
+    int f1 = f0 + 1;
+    while (f1 == p || f1 == c) ++f1;
+    prev = bufs[p];
+    cur = bufs[c];
+    outa = bufs[D >= 2 ? f0 : f1];
+    outb = bufs[D >= 2 ? f1 : f0];
+    return true;
+}
+
 // r_0 (and the partials of <r_0|r_0>, slot 0) into `cur` over the solve's work
 // items (the owned sites of each tile and segment).
 template <typename S, bool WIDE>
@@ -69,13 +109,7 @@ __global__ __launch_bounds__(TB_BLOCK) void k_init_tb(const Inst *__restrict__ t
 //
 // Solo launches (bmap == nullptr) take the instance tab[0], the step n = arg and
 // the four buffer roles from the arguments.  Batched launches take the instance
-// from the block map and run one pass of its current chunk: tbfull passes of
-// the full depth tbh (launch argument j = 0 .. tbfull-1, D = tbh), then one of
-// depth tbrem (launch argument -1, D = tbrem).  Pass j starts at step
-// step0 + j * tbh, and its buffer roles follow from the pair (tbp, tbc) that
-// held (r_{step0-1}, r_{step0}): a pass of depth >= 2 writes its two outputs to
-// the other two buffers in ascending order, so pass j reads the pair itself
-// (j = 0), its complement (j odd) or the pair in ascending order (j even).
+// from the block map and run one pass of its current chunk (tb_pass_roles).
 template <typename S, int OPK, bool WIDE, bool NT, int D>
 __global__ __launch_bounds__(TB_BLOCK) __attribute__((amdgpu_waves_per_eu(TB_WAVES_PER_EU(S, D)))) void k_step_tbd(
     const Inst *__restrict__ tab, const uint32_t *__restrict__ bmap, int32_t arg, const void *prev, const void *cur,
@@ -90,36 +124,7 @@ __global__ __launch_bounds__(TB_BLOCK) __attribute__((amdgpu_waves_per_eu(TB_WAV
     if (hb == NO_INSTANCE) return;
     const Inst I = tab[hb];
     int32_t n = arg;
-    if (bmap) {
-        // arg >= 0: full-depth pass arg of the chunk; arg < 0: the remainder pass (depth D)
-        int32_t j = arg;
-        if (arg < 0) {
-            if (I.tbrem != D) return;
-            j = I.tbfull;
-        } else if (j >= I.tbfull) {
-            return;
-        }
-        n = I.step0 + j * I.tbh;
-        void *const bufs[4] = {I.buf0, I.buf1, I.tb2, I.tb3};
-        int p = I.tbp, c = I.tbc;
-        if (j > 0) {
-            const int lo = min(p, c), hi = max(p, c);
-            int f0 = 0;
-            while (f0 == lo || f0 == hi) ++f0;
-            int f1 = f0 + 1;
-            while (f1 == lo || f1 == hi) ++f1;
-            p = (j & 1) ? f0 : lo;
-            c = (j & 1) ? f1 : hi;
-        }
-        int f0 = 0;
-        while (f0 == p || f0 == c) ++f0;
-        int f1 = f0 + 1;
-        while (f1 == p || f1 == c) ++f1;
-        prev = bufs[p];
-        cur = bufs[c];
-        outa = bufs[D >= 2 ? f0 : f1];
-        outb = bufs[D >= 2 ? f1 : f0];
-    }
+    if (bmap && !tb_pass_roles(I, arg, D, n, prev, cur, outa, outb)) return;
     const uint32_t C = I.C, Lx = I.P, Ly = I.Lm;
     const uint32_t h = (uint32_t)I.tbh, Wn = TB_BLOCK / C, Tn = Wn - 2 * h;   // h >= D
     const uint32_t tid = threadIdx.x, s = tid / C, c = tid - s * C;

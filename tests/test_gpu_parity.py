@@ -78,8 +78,10 @@ def _csr_with_empty_rows():
 CASES = _cases()
 
 
-# execution paths: one workgroup with the vectors in LDS (small), march kernels, flat kernels
-PATHS = {"small": dict(small=1), "march": dict(small=0, march=1), "flat": dict(small=0, march=0)}
+# execution paths: one workgroup with the vectors in LDS (small), one-step march kernels, several
+# steps per pass (temporal blocking: 2D and 3D lattices), flat kernels
+PATHS = {"small": dict(small=1), "march": dict(small=0, march=1, tblock=0),
+         "blocked": dict(small=0, march=1, tblock=-1, tb3=1), "flat": dict(small=0, march=0)}
 
 
 @pytest.mark.parametrize("path", list(PATHS))
@@ -212,7 +214,11 @@ def test_batched_waves_bitwise(prec):
         hs.append(kpm.Hamiltonian(op, a, b, prec))
     Ms, Rs = [40, 64, 90, 50, 33, 128], [3, 4, 3, 5, 2, 4]
     seeds, insts = [5, 6, 7, 8, 9, 10], [1, 2, 3, 4, 5, 6]
-    solo = [kpm.moments(h, Ms[k], Rs[k], wl.VEC_PHASE, seeds[k], insts[k]).cpu().numpy() for k, h in enumerate(hs)]
+    # static batches take one step per pass, so their solo reference does too (a blocked solo solve
+    # forms the same vectors but sums its dot partials over other work items)
+    with kpm.launch_settings(tblock=0):
+        solo = [kpm.moments(h, Ms[k], Rs[k], wl.VEC_PHASE, seeds[k], insts[k]).cpu().numpy()
+                for k, h in enumerate(hs)]
     for wave in (1, 0, 192):
         with kpm.launch_settings(wave_mib=wave):
             got = [m.cpu().numpy() for m in kpm.moments_batched(hs, Ms, Rs, wl.VEC_PHASE, seeds, insts)]

@@ -81,6 +81,7 @@ def test_argument_validation_without_device(L):
     assert L.kpm_set_launch(5, 2) == 1
     assert L.kpm_set_launch(9, 2) == 1          # depth keys: 0 one step, 1 two, 3..6, -1 default; 2 is none
     assert L.kpm_set_launch(9, 7) == 1
+    assert L.kpm_set_launch(10, 2) == 1         # 3D two-step passes: -1, 0 or 1
     assert L.kpm_set_launch(99, 1) == 1
     d = kpm.HamDesc()
     d.kind = 3
@@ -104,10 +105,10 @@ def test_lanczos_argument_validation(L):
 def test_launch_settings_roundtrip(L):
     old = kpm.get_launch()
     with kpm.launch_settings(elems_per_thread=2, max_blocks=1024, march=0, march_items=64, xcd_split=3, alternate=0,
-                             small=0, streaming=0, wave_mib=0, tblock=0):
+                             small=0, streaming=0, wave_mib=0, tblock=0, tb3=1):
         assert kpm.get_launch() == {"elems_per_thread": 2, "max_blocks": 1024, "march": 0, "march_items": 64,
                                     "xcd_split": 3, "alternate": 0, "small": 0, "streaming": 0, "wave_mib": 0,
-                                    "tblock": 0}
+                                    "tblock": 0, "tb3": 1}
     assert kpm.get_launch() == old
 
 
