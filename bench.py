@@ -433,6 +433,52 @@ def serving_leg(n_requests, logN_max, load, seed=1005, fp64_stable=0.0, capacity
     return out
 
 
+def serving_at_rate(n_requests, logN_max, rate, paths=("fp32", "fp64"), seed=1005):
+    """The config-5 trace (same requests as serving_leg) arriving at `rate` requests per second
+    (wall clock), served by the FP32 continuous-batching server and/or replayed through the plain
+    FP64 first-come-first-served path.  Reports latency, isolated service times and throughput per
+    path; a long record can thus be split over several runs at one fixed rate."""
+    import numpy as np
+    import paper_1105_5481_amd as kpm
+    from paper_1105_5481_amd import workloads as wl
+    from paper_1105_5481_amd.serve import KPMRequest, Server, latency_stats
+    stream = wl.config5_stream(n_requests, rate=1.0, seed=seed, logN_max=logN_max)
+    gaps = np.diff([0.0] + [r.arrival for r in stream])
+    arrivals = np.cumsum(gaps / rate)
+    reqs = [KPMRequest(op=r.lattice, M=r.M, R=r.R, vec=r.vec, seed=r.seed, instance=0, arrival=t, rid=r.rid)
+            for r, t in zip(stream, arrivals)]
+    alg_bytes = 0.0
+    for r in stream:
+        cplx = r.lattice.hop == wl.HOP_SPIN or r.vec == wl.VEC_PHASE
+        alg_bytes += (r.M // 2) * algorithmic_bytes_per_step(r.lattice.N, r.R, cplx, 4, r.lattice.onsite is not None,
+                                                             r.lattice.dim if r.lattice.hop == wl.HOP_SPIN else 0)
+    out = {"requests": n_requests, "logN_range": [12, logN_max], "arrival_rate_req_per_s": rate,
+           "trace_seconds": float(arrivals[-1])}
+    log(f"bench: serving at {rate:.3f} req/s, trace over {arrivals[-1]:.1f} s")
+    for path in paths:
+        if path == "fp32":
+            srv = Server(prec=kpm.F32, max_active=64, chunk=32)
+        else:
+            srv = Server(prec=kpm.F64, max_active=1, chunk=64)
+        t0 = time.perf_counter()
+        res = srv.run(reqs, clock="wall", progress=log, timeout=7200.0)
+        wall = time.perf_counter() - t0
+        conc = srv.max_concurrent
+        srv.close()
+        ok = [r for r in res if r.status == "ok"]
+        svc = np.array([r.t_done - r.t_admit for r in ok])
+        rec = {"latency": latency_stats(res), "wall_seconds": wall, "max_concurrent_solves": conc,
+               "isolated_service_ms": {"p50": float(np.percentile(svc, 50) * 1e3),
+                                       "p99": float(np.percentile(svc, 99) * 1e3), "mean": float(svc.mean() * 1e3)},
+               "service_capacity_req_per_s": len(svc) / svc.sum() if path == "fp64" else None,
+               "statuses": {st: sum(1 for r in res if r.status == st) for st in sorted({r.status for r in res})}}
+        if path == "fp32":
+            rec["throughput_GBps_algorithmic"] = alg_bytes / wall / 1e9
+        out[path] = rec
+        log(f"bench: {path} at {rate:.3f} req/s: {latency_stats(res)}")
+    return out
+
+
 def cpu_baseline(lat, a, b, vec, seed):
     """The oracle (plain FP64 CPU code) on a bounded sample of the same lattice."""
     import oracle
@@ -625,6 +671,9 @@ def main():
                     help="config5: also serve at this fraction of the FP64 capacity (0: off)")
     ap.add_argument("--serve-load", type=lambda v: [float(x) for x in v.split(",")], default=[0.7],
                     help="offered load(s) as a fraction of the measured FP32 capacity, comma separated")
+    ap.add_argument("--serve-rate", type=float, default=0.0,
+                    help="config5: serve the trace at this arrival rate (req/s) through --serve-paths and stop")
+    ap.add_argument("--serve-paths", default="fp32,fp64", help="config5 with --serve-rate: fp32, fp64 or both")
     ap.add_argument("--serve-capacity-only", action="store_true",
                     help="config5: measure the FP32 server's capacity (all requests at t = 0) and stop")
     ap.add_argument("--tpt", type=int, default=0, help="chunks per thread per tile (1, 2, 4)")
@@ -699,6 +748,13 @@ def main():
                    streaming=None if args.streaming < 0 else args.streaming,
                    wave_mib=None if args.wave_mib < 0 else args.wave_mib,
                    tblock=None if args.tblock < 0 else args.tblock)
+    if args.workload == "config5" and args.serve_rate > 0:
+        sv = serving_at_rate(args.serve_requests, args.serve_logn_max, args.serve_rate,
+                             [p for p in args.serve_paths.split(",") if p])
+        print(json.dumps({"metric": "p50/p99 solve latency under a Poisson request stream", "unit": "ms",
+                          "n_gpus": 1, "data": "synthetic", "higher_is_better": False,
+                          "config": {"workload": WORKLOAD_TEXT["config5"]}, "serving": sv}), flush=True)
+        return
     if args.workload == "config5":
         # the serving record alone: FP32 continuous batching vs the plain FP64 FCFS path
         sv = serving_leg(args.serve_requests, args.serve_logn_max, args.serve_load, fp64_stable=args.serve_fp64_stable,
