@@ -353,7 +353,7 @@ def pmc_summary(root):
         print(f"{name} grid={grid}: {vals}")
 
 
-def serving_leg(n_requests, logN_max, load, seed=1005, fp64_stable=0.0, capacity_only=False):
+def serving_leg(n_requests, logN_max, load, seed=1005, fp64_stable=0.0, capacity_only=False, slots=64):
     """Config-5 recipe (Poisson arrivals; N log-uniform from 2^12 up to 2^logN_max; 2D/3D; real or
     spin hopping; M in {256, 1024, 4096, 8192}; R in [8, 64]).  Capacity of the batched FP32 server
     is measured with every request present at t = 0; a wall-clock trace at each offered load
@@ -378,7 +378,7 @@ def serving_leg(n_requests, logN_max, load, seed=1005, fp64_stable=0.0, capacity
         cplx = r.lattice.hop == wl.HOP_SPIN or r.vec == wl.VEC_PHASE
         alg_bytes += (r.M // 2) * algorithmic_bytes_per_step(r.lattice.N, r.R, cplx, 4, r.lattice.onsite is not None,
                                                              r.lattice.dim if r.lattice.hop == wl.HOP_SPIN else 0)
-    srv = Server(prec=kpm.F32, max_active=64, chunk=32)
+    srv = Server(prec=kpm.F32, max_active=slots, chunk=32)
     t0 = time.perf_counter()
     res = srv.run(reqs([0.0] * n_requests), clock="chunks", progress=log)
     makespan = time.perf_counter() - t0
@@ -395,7 +395,7 @@ def serving_leg(n_requests, logN_max, load, seed=1005, fp64_stable=0.0, capacity
     for ld in loads:
         arrivals = np.cumsum(gaps / (ld * capacity))
         log(f"bench: load {ld}: trace over {arrivals[-1]:.2f} s")
-        srv = Server(prec=kpm.F32, max_active=64, chunk=32)
+        srv = Server(prec=kpm.F32, max_active=slots, chunk=32)
         served = srv.run(reqs(arrivals), clock="wall", progress=log)
         conc = srv.max_concurrent
         srv.close()
@@ -418,7 +418,7 @@ def serving_leg(n_requests, logN_max, load, seed=1005, fp64_stable=0.0, capacity
         rate = fp64_stable * out["loads"][-1]["fp64_capacity_req_per_s"]
         arrivals = np.cumsum(gaps / rate)
         log(f"bench: FP64-stable rate {rate:.2f} req/s: trace over {arrivals[-1]:.2f} s")
-        srv = Server(prec=kpm.F32, max_active=64, chunk=32)
+        srv = Server(prec=kpm.F32, max_active=slots, chunk=32)
         served = srv.run(reqs(arrivals), clock="wall", progress=log)
         srv.close()
         srv = Server(prec=kpm.F64, max_active=1, chunk=64)
@@ -433,7 +433,7 @@ def serving_leg(n_requests, logN_max, load, seed=1005, fp64_stable=0.0, capacity
     return out
 
 
-def serving_at_rate(n_requests, logN_max, rate, paths=("fp32", "fp64"), seed=1005):
+def serving_at_rate(n_requests, logN_max, rate, paths=("fp32", "fp64"), seed=1005, slots=64):
     """The config-5 trace (same requests as serving_leg) arriving at `rate` requests per second
     (wall clock), served by the FP32 continuous-batching server and/or replayed through the plain
     FP64 first-come-first-served path.  Reports latency, isolated service times and throughput per
@@ -457,7 +457,7 @@ def serving_at_rate(n_requests, logN_max, rate, paths=("fp32", "fp64"), seed=100
     log(f"bench: serving at {rate:.3f} req/s, trace over {arrivals[-1]:.1f} s")
     for path in paths:
         if path == "fp32":
-            srv = Server(prec=kpm.F32, max_active=64, chunk=32)
+            srv = Server(prec=kpm.F32, max_active=slots, chunk=32)
         else:
             srv = Server(prec=kpm.F64, max_active=1, chunk=64)
         t0 = time.perf_counter()
@@ -667,13 +667,14 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=160)
     ap.add_argument("--serve-logn-max", type=float, default=18.0)
-    ap.add_argument("--serve-fp64-stable", type=float, default=0.0,
-                    help="config5: also serve at this fraction of the FP64 capacity (0: off)")
+    ap.add_argument("--serve-fp64-stable", type=float, default=0.8,
+                    help="also serve at this fraction of the FP64 capacity, a rate the plain path sustains (0: off)")
     ap.add_argument("--serve-load", type=lambda v: [float(x) for x in v.split(",")], default=[0.7],
                     help="offered load(s) as a fraction of the measured FP32 capacity, comma separated")
     ap.add_argument("--serve-rate", type=float, default=0.0,
                     help="config5: serve the trace at this arrival rate (req/s) through --serve-paths and stop")
     ap.add_argument("--serve-paths", default="fp32,fp64", help="config5 with --serve-rate: fp32, fp64 or both")
+    ap.add_argument("--serve-slots", type=int, default=64, help="batch slots of the FP32 server")
     ap.add_argument("--serve-capacity-only", action="store_true",
                     help="config5: measure the FP32 server's capacity (all requests at t = 0) and stop")
     ap.add_argument("--tpt", type=int, default=0, help="chunks per thread per tile (1, 2, 4)")
@@ -750,7 +751,7 @@ def main():
                    tblock=None if args.tblock < 0 else args.tblock)
     if args.workload == "config5" and args.serve_rate > 0:
         sv = serving_at_rate(args.serve_requests, args.serve_logn_max, args.serve_rate,
-                             [p for p in args.serve_paths.split(",") if p])
+                             [p for p in args.serve_paths.split(",") if p], slots=args.serve_slots)
         print(json.dumps({"metric": "p50/p99 solve latency under a Poisson request stream", "unit": "ms",
                           "n_gpus": 1, "data": "synthetic", "higher_is_better": False,
                           "config": {"workload": WORKLOAD_TEXT["config5"]}, "serving": sv}), flush=True)
@@ -758,7 +759,7 @@ def main():
     if args.workload == "config5":
         # the serving record alone: FP32 continuous batching vs the plain FP64 FCFS path
         sv = serving_leg(args.serve_requests, args.serve_logn_max, args.serve_load, fp64_stable=args.serve_fp64_stable,
-                         capacity_only=args.serve_capacity_only)
+                         capacity_only=args.serve_capacity_only, slots=args.serve_slots)
         print(json.dumps({"metric": "p50/p99 solve latency under a Poisson request stream", "unit": "ms",
                           "n_gpus": 1, "data": "synthetic", "higher_is_better": False,
                           "config": {"workload": WORKLOAD_TEXT["config5"]}, "serving": sv}), flush=True)
@@ -784,7 +785,8 @@ def main():
                                          "Infinity Cache, so the rate is partly cache bandwidth")
     if not args.no_serve:
         log("bench: serving leg")
-        out["serving"] = serving_leg(args.serve_requests, args.serve_logn_max, args.serve_load[0])
+        out["serving"] = serving_leg(args.serve_requests, args.serve_logn_max, args.serve_load[0],
+                                     fp64_stable=args.serve_fp64_stable, slots=args.serve_slots)
     print(json.dumps(out), flush=True)
 
 
