@@ -29,13 +29,13 @@ def _spin2d(Lx, Ly, seed):
 
 def _cases():
     return [
-        # (name, lattice, vector kind, solve mode expected for FP32: 3 blocked, 1 march)
+        # (name, lattice, vector kind, solve mode expected for FP32: 3 blocked 2D, 4 blocked 3D, 1 march)
         ("square_256x16_anderson_pm1", wl.Lattice(dim=2, L=(256, 16, 1), t=1.0,
                                                    onsite=wl.anderson_onsite(4096, 2.0, 41)), wl.VEC_RADEMACHER, 3),
         ("spin2d_128x32_phase", _spin2d(128, 32, 42), wl.VEC_PHASE, 3),
         ("spin2d_64x64_phase", _spin2d(64, 64, 43), wl.VEC_PHASE, 1),
         ("spin3d_16_phase", wl.spin_cubic_lattice(16, seed=44), wl.VEC_PHASE, 1),
-        ("cubic_16_anderson_pm1", wl.cubic_lattice(16, t=1.0, W=1.0, seed=45), wl.VEC_RADEMACHER, 1),
+        ("cubic_16_anderson_pm1", wl.cubic_lattice(16, t=1.0, W=1.0, seed=45), wl.VEC_RADEMACHER, 4),
     ]
 
 
