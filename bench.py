@@ -46,15 +46,32 @@ TB_KERNEL = {d: "k_step_tbd<float, OP_REAL2, %d> (%d step%s per launch)" % (d, d
 TB3_KERNEL = "k_step_tb3<float, OP_SPIN3, 2> (2 steps per launch)"
 
 
-def tb_depth(tblock, prec, C=16, spin=False):
+def tb_groups(C, Lx, group=8):
+    """Chunk groups of a 2D blocked solve (the library's rule for KPM_LAUNCH_TB_GROUP = group):
+    none when the whole site already gives a window of 32 sites or more, else the most groups that
+    keep at least `group` chunks per group and a window of 512 / (C / G) sites within the row."""
+    best = 1
+    if group <= 0 or 512 // C >= 32:
+        return best
+    for G in range(2, C + 1):
+        if C % G:
+            continue
+        if C // G < group or Lx < 512 // (C // G):
+            break
+        best = G
+    return best
+
+
+def tb_depth(tblock, prec, C=16, spin=False, Lx=1 << 30, group=8):
     """Steps of the deepest pass of a temporally blocked solve for a KPM_LAUNCH_TBLOCK value (the
     library's rule: -1 gives 4 for FP32 real hopping and 3 otherwise; 1 pairs; at most a quarter of
-    the window of 512 / C sites, C = 16-byte chunks per site)."""
+    the window of 512 / Cg sites, Cg = 16-byte chunks per site in one chunk group)."""
     if tblock < 0:
         d = 3 if (prec == 0 or spin) else 4
     else:
         d = tblock if tblock >= 3 else 2
-    return min(d, 512 // C // 4)
+    Cg = C // tb_groups(C, Lx, group)
+    return min(d, 512 // Cg // 4)
 
 
 def kpm_default_tblock():
@@ -589,7 +606,8 @@ def bench_lattice(args, workload, steps, warmup, fp64=True, cpu=True):
     if solve_mode.get(kpm.F32) == 4:
         depth = 2
     else:
-        depth = tb_depth(kpm.get_launch()["tblock"], kpm.F32, chunks, lat.hop == wl.HOP_SPIN) if tblocked else 1
+        lk = kpm.get_launch()
+        depth = tb_depth(lk["tblock"], kpm.F32, chunks, lat.hop == wl.HOP_SPIN, lat.L[0], lk["tb_group"]) if tblocked else 1
     nrec = K if tblocked else K - 1          # begin runs step 0 except with temporal blocking
     step_us = rec32 * 1e3 / nrec             # per recursion step
     launch_us = step_us * depth
@@ -686,6 +704,8 @@ def main():
     ap.add_argument("--streaming", type=int, default=-1)
     ap.add_argument("--wave-mib", type=int, default=-1, help="batched solves: MiB of state per wave, 0 = one wave")
     ap.add_argument("--tblock", type=int, default=-1, help="2D lattices: steps per pass, 1 two, 3..6, 0 one step")
+    ap.add_argument("--tb-group", type=int, default=-1, help="2D blocked solves: least chunks per chunk group (0: one group)")
+    ap.add_argument("--tb3", type=int, default=-2, help="3D two-step passes: 1 on, 0 off, -1 FP32 real hopping")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain 1 GiB device copy three times (counter calibration under rocprofv3)")
     ap.add_argument("--pmc-summary", metavar="DIR",
@@ -748,7 +768,9 @@ def main():
                    alternate=None if args.alternate < 0 else args.alternate,
                    streaming=None if args.streaming < 0 else args.streaming,
                    wave_mib=None if args.wave_mib < 0 else args.wave_mib,
-                   tblock=None if args.tblock < 0 else args.tblock)
+                   tblock=None if args.tblock < 0 else args.tblock,
+                   tb_group=None if args.tb_group < 0 else args.tb_group,
+                   tb3=None if args.tb3 < -1 else args.tb3)
     if args.workload == "config5" and args.serve_rate > 0:
         sv = serving_at_rate(args.serve_requests, args.serve_logn_max, args.serve_rate,
                              [p for p in args.serve_paths.split(",") if p], slots=args.serve_slots)

@@ -374,8 +374,9 @@ kpm_status kpm_start_vectors(int32_t vec, int32_t complex_layout, uint64_t seed,
  *                                vectors and operators total at most this many MiB (default
  *                                224, so a wave stays in the Infinity Cache); a wave runs all
  *                                its recursion steps before the next starts.  0 = one wave
- *   KPM_LAUNCH_TBLOCK            solves on 2D lattices (real or spin hopping; C <= 64 chunks
- *                                per site, windows of floor(512/C) sites, L_x >= 512/C) take
+ *   KPM_LAUNCH_TBLOCK            solves on 2D lattices (real or spin hopping; windows of
+ *                                floor(512/Cg) sites of Cg <= 64 chunks each (KPM_LAUNCH_TB_GROUP),
+ *                                L_x >= 512/Cg) take
  *                                several recursion steps per pass over the vectors (temporal
  *                                blocking; 4 vector buffers instead of 2, bitwise the same
  *                                vectors; in a dynamic batch they share blocked launches):
@@ -395,6 +396,12 @@ kpm_status kpm_start_vectors(int32_t vec, int32_t complex_layout, uint64_t seed,
  *                                lattice, -1 (default) for FP32 recursions with real
  *                                hopping only, 0 never.  Needs L_x L_y <= 1024 sites or
  *                                L_x <= 170
+ *   KPM_LAUNCH_TB_GROUP          2D temporally blocked solves with more than 16 chunks per
+ *                                site split its C chunks into groups of at least this many
+ *                                chunks (default 8 = 128 bytes, 0 = one group), as many groups
+ *                                as keep the window of floor(512 / chunks per group) sites
+ *                                within L_x: a wider window recomputes and re-reads a smaller
+ *                                halo share
  * The partial sums of the dot products are formed per work item, so the
  * moments do not depend on the grid (MAX_BLOCKS) nor on the batch an instance
  * runs in; the other keys change the work items and with them the order in
@@ -411,7 +418,8 @@ typedef enum {
     KPM_LAUNCH_STREAMING = 7,
     KPM_LAUNCH_WAVE_MIB = 8,
     KPM_LAUNCH_TBLOCK = 9,
-    KPM_LAUNCH_TB3 = 10
+    KPM_LAUNCH_TB3 = 10,
+    KPM_LAUNCH_TB_GROUP = 11
 } kpm_launch_key;
 kpm_status kpm_set_launch(int32_t key, int32_t value);
 kpm_status kpm_get_launch(int32_t key, int32_t *value);

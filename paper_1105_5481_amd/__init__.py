@@ -622,7 +622,7 @@ def start_vectors(vec: int, complex_layout: bool, seed: int, instance: int, N: i
 LAUNCH_ELEMS_PER_THREAD, LAUNCH_MAX_BLOCKS, LAUNCH_MARCH, LAUNCH_MARCH_ITEMS, LAUNCH_XCD_SPLIT, LAUNCH_ALTERNATE, \
     LAUNCH_SMALL, LAUNCH_STREAMING = range(8)
 _LAUNCH_KEYS = {"elems_per_thread": 0, "max_blocks": 1, "march": 2, "march_items": 3, "xcd_split": 4, "alternate": 5,
-                "small": 6, "streaming": 7, "wave_mib": 8, "tblock": 9, "tb3": 10}
+                "small": 6, "streaming": 7, "wave_mib": 8, "tblock": 9, "tb3": 10, "tb_group": 11}
 
 
 def set_launch(**kw):

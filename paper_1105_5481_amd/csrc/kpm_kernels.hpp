@@ -83,6 +83,7 @@ struct Inst {
     void *tb2, *tb3;   // temporal blocking: buffers 2 and 3 of four (buf0, buf1 are 0 and 1)
     int32_t tbp, tbc;  // ... and which of them hold r_{step0-1}, r_{step0} (batched passes)
     int32_t tbfull, tbrem;  // batched passes of this chunk: tbfull of depth tbh, then one of depth tbrem
+    uint32_t tbg;      // 2D temporal blocking: chunk groups per site (a work item covers C / tbg chunks)
     double *partial;   // [pslots][tiles][4]
     double *dots;      // [K+1][4] = (nn.hi, nn.lo, nm.hi, nm.lo)
     double *mu;        // [M]

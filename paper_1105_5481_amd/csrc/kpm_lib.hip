@@ -506,6 +506,7 @@ struct Plan {
     size_t esz;
     size_t part_bytes, dots_bytes, buf_bytes;
     uint32_t nbuf;    // vector buffers (2, or 4 with temporal blocking)
+    uint32_t tbg;     // 2D temporal blocking: chunk groups per site
     int32_t tbh;      // temporal blocking: x-tile halo = steps of the deepest pass (1 .. 6)
     uint64_t state;   // bytes the recursion touches per step (vectors + operator)
 };
@@ -525,6 +526,27 @@ int tb_depth(int prec, int opk)
 int tb_halo(int prec, int opk, uint32_t C)
 {
     return std::min<int>(tb_depth(prec, opk), (int)(TB_BLOCK / C / 4));
+}
+
+// Chunk groups of a 2D blocked solve whose window would be narrower than 32
+// sites (more than 16 chunks per site): the most groups (the widest window, so
+// the smallest halo share) that keep at least g_tb_group chunks (128 bytes at
+// 8) per site in a group and a window no wider than the row.  0 turns grouping
+// off.  Measured on the 2048^2 lattice, R = 64: FP64 (32 chunks, window 16 ->
+// 64 sites) 1443 -> 1306 ms per solve; FP32 (16 chunks, window 32 -> 64) 478 ->
+// 506 ms, hence no grouping from 32-site windows up.
+int g_tb_group = 8;
+uint32_t tb_groups(uint32_t C, uint32_t Lx)
+{
+    uint32_t best = 1;
+    if (g_tb_group <= 0 || TB_BLOCK / C >= 32) return best;
+    for (uint32_t G = 2; G <= C; ++G) {
+        if (C % G) continue;
+        const uint32_t Cg = C / G;
+        if (Cg < (uint32_t)g_tb_group || Lx < TB_BLOCK / Cg) break;
+        best = G;
+    }
+    return best;
 }
 
 // Store kind for r_{n+1}: it is read again as r_n by the next step, so keep it
@@ -592,27 +614,32 @@ bool make_plan(const kpm_ham *h, int32_t M, int32_t R, int32_t vec, Plan &p, boo
         p.tiles = SMALL_WAVES;   // per-wave dot partials
         p.xcd = 0;
     } else if (allow_tb && g_tblock && g_march && (h->opk == OP_REAL2 || h->opk == OP_SPIN2) &&
-               tb_halo(h->prec, h->opk, p.C) >= 2 && h->L[0] >= TB_BLOCK / p.C &&
-               h->L[1] >= 2 * tb_halo(h->prec, h->opk, p.C)) {
-        // several steps per pass: windows of floor(TB_BLOCK/C) sites (the threads beyond
-        // window * C idle), x-tiles of the window less 2 tbh halo sites, segments of rows
+               tb_halo(h->prec, h->opk, p.C / tb_groups(p.C, (uint32_t)h->L[0])) >= 2 &&
+               h->L[0] >= TB_BLOCK / (p.C / tb_groups(p.C, (uint32_t)h->L[0])) &&
+               h->L[1] >= 2 * tb_halo(h->prec, h->opk, p.C / tb_groups(p.C, (uint32_t)h->L[0]))) {
+        // several steps per pass: the site's chunks in tbg groups, windows of
+        // floor(TB_BLOCK/Cg) sites of one group (Cg = C/tbg; threads beyond window * Cg
+        // idle), x-tiles of the window less 2 tbh halo sites, segments of rows
         p.mode = MODE_TB;
         p.nbuf = 4;
-        p.tbh = tb_halo(h->prec, h->opk, p.C);
-        const uint32_t Tn = TB_BLOCK / p.C - 2 * (uint32_t)p.tbh;
+        p.tbg = tb_groups(p.C, (uint32_t)h->L[0]);
+        const uint32_t Cg = p.C / p.tbg;
+        p.tbh = tb_halo(h->prec, h->opk, Cg);
+        const uint32_t Tn = TB_BLOCK / Cg - 2 * (uint32_t)p.tbh;
         p.P = (uint32_t)h->L[0];
         p.Lm = (uint32_t)h->L[1];
         p.nct = (p.P + Tn - 1) / Tn;
         // more and shorter segments than the one-step kernels (8x the item target;
         // measured on the 2048^2 lattice with two-step passes: 4096 items 455 us per
         // step, 512 items 554 us)
+        const uint64_t units = (uint64_t)p.nct * p.tbg;
         const uint64_t target = 8ull * (uint64_t)g_march_items;
-        uint32_t nseg = (uint32_t)((target + p.nct - 1) / p.nct);
+        uint32_t nseg = (uint32_t)((target + units - 1) / units);
         nseg = std::max<uint32_t>(1, std::min<uint32_t>(nseg, std::max<uint32_t>(1, p.Lm / 8)));
         p.S = (p.Lm + nseg - 1) / nseg;
         p.nseg = (p.Lm + p.S - 1) / p.S;
-        p.tiles = p.nct * p.nseg;
-        p.xcd = p.nct >= 8 ? 1 : 0;
+        p.tiles = (uint32_t)(units * p.nseg);
+        p.xcd = units >= 8 ? 1 : 0;
     } else if (allow_tb && g_tblock && g_march &&
                (g_tb3 > 0 ? (h->opk == OP_REAL3 || h->opk == OP_SPIN3)
                           : (g_tb3 < 0 && h->opk == OP_REAL3 && h->prec == KPM_F32)) &&
@@ -705,6 +732,7 @@ void fill_inst(const kpm_ham *h, const Plan &p, int32_t M, int32_t R, int32_t ve
     I.step0 = 0;
     I.pslots = p.P_slots;
     I.tbh = p.tbh;
+    I.tbg = p.tbg ? p.tbg : 1;
     I.seed = seed;
     I.instance = instance;
     I.norm = (vec == KPM_VEC_UNIT) ? (double)R : (double)h->N * (double)R;
@@ -1381,7 +1409,8 @@ uint32_t place_blocks(std::vector<Inst> &ins, std::vector<uint32_t> &map)
     auto cost = [&](uint32_t r) { return ins[r].nel ? (uint64_t)ins[r].nel : (uint64_t)ins[r].nb; };
     auto units = [&](uint32_t r) {
         if (ins[r].mode == MODE_TB3) return ins[r].nct * ins[r].C;
-        return (ins[r].mode == MODE_MARCH || ins[r].mode == MODE_TB) ? ins[r].nct : ins[r].tiles;
+        if (ins[r].mode == MODE_TB) return ins[r].nct * ins[r].tbg;
+        return ins[r].mode == MODE_MARCH ? ins[r].nct : ins[r].tiles;
     };
     std::stable_sort(small.begin(), small.end(), [&](uint32_t a, uint32_t b) { return cost(a) > cost(b); });
     uint64_t total = 0;
@@ -2193,6 +2222,10 @@ kpm_status kpm_set_launch(int32_t key, int32_t value)
         if (value < -1 || value > 1) return KPM_ERR_INVALID_ARG;
         g_tb3 = value;
         return KPM_OK;
+    case KPM_LAUNCH_TB_GROUP:
+        if (value < 0 || value > 512) return KPM_ERR_INVALID_ARG;
+        g_tb_group = value;
+        return KPM_OK;
     }
     return KPM_ERR_INVALID_ARG;
 }
@@ -2212,6 +2245,7 @@ kpm_status kpm_get_launch(int32_t key, int32_t *value)
     case KPM_LAUNCH_WAVE_MIB: *value = g_wave_mib; return KPM_OK;
     case KPM_LAUNCH_TBLOCK: *value = g_tblock; return KPM_OK;
     case KPM_LAUNCH_TB3: *value = g_tb3; return KPM_OK;
+    case KPM_LAUNCH_TB_GROUP: *value = g_tb_group; return KPM_OK;
     }
     return KPM_ERR_INVALID_ARG;
 }

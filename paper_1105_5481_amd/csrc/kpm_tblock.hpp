@@ -2,9 +2,11 @@
 // several steps per pass over the vectors.
 //
 // A work item is an x-tile of T sites times a segment of rows (the march axis
-// y).  Its block holds a window of W = TB_BLOCK / C sites (T = W - 2h owned
-// plus h halo sites on each side, h = the depth of the solve's deepest passes),
-// one thread per 16-byte chunk.  A pass of D <= h steps reads r_{n-1} and r_n
+// y) times one group of the site's chunks (C / G of its C 16-byte chunks, G
+// groups; smaller groups widen the window and so cut the halo's share).  Its
+// block holds a window of W = TB_BLOCK / (C / G) sites (T = W - 2h owned plus
+// h halo sites on each side, h = the depth of the solve's deepest passes), one
+// thread per 16-byte chunk of the group.  A pass of D <= h steps reads r_{n-1} and r_n
 // and writes r_{n+D-1} and r_{n+D} (for D = 1 only r_{n+1}); the halo
 // recomputation means r_{n-1} and r_n are read by neighbouring tiles while the
 // pass runs, so the outputs go to the two free buffers of four.  r_{n-1} (read
@@ -68,14 +70,15 @@ __global__ __launch_bounds__(TB_BLOCK) void k_init_tb(const Inst *__restrict__ t
     typedef typename V16<S>::T T;
     typedef Mem<S, WIDE> G;
     const Inst I = tab[0];
-    const uint32_t C = I.C, Lx = I.P, Ly = I.Lm;
-    const uint32_t h = (uint32_t)I.tbh, Wn = TB_BLOCK / C, Tn = Wn - 2 * h;
-    const uint32_t tid = threadIdx.x, s = tid / C, c = tid - s * C;
-    const ItemRange ir = item_range(I, I.nct, I.nseg);
+    const uint32_t C = I.C, Gs = I.tbg, Cg = C / Gs, Lx = I.P, Ly = I.Lm;
+    const uint32_t h = (uint32_t)I.tbh, Wn = TB_BLOCK / Cg, Tn = Wn - 2 * h;
+    const uint32_t tid = threadIdx.x, s = tid / Cg, cl = tid - s * Cg;
+    const ItemRange ir = item_range(I, I.nct * Gs, I.nseg);
     for (uint32_t it = ir.first; it < ir.count; it += ir.stride) {
         const uint32_t sl = it / ir.nu;
         const uint32_t sg = ir.sb + sl;
-        const uint32_t tx = ir.ub + (it - sl * ir.nu);
+        const uint32_t unit = ir.ub + (it - sl * ir.nu);
+        const uint32_t tx = unit / Gs, c = (unit - tx * Gs) * Cg + cl;
         const uint32_t x0 = tx * Tn;
         const uint32_t xend = min(x0 + Tn, Lx);
         const uint32_t x = (x0 + Lx - h + s) % Lx;
@@ -89,7 +92,8 @@ __global__ __launch_bounds__(TB_BLOCK) void k_init_tb(const Inst *__restrict__ t
                 G::st(cur, i * C + c, v);
                 a.norm_only(v);
             }
-        block_reduce_store<Dots<S>::DD, TB_BLOCK>(a.s0, a.c0, a.s1, a.c1, I.partial + (size_t)(sg * I.nct + tx) * 4);
+        block_reduce_store<Dots<S>::DD, TB_BLOCK>(a.s0, a.c0, a.s1, a.c1,
+                                                  I.partial + (size_t)(sg * I.nct * Gs + unit) * 4);
     }
 }
 
@@ -125,27 +129,28 @@ __global__ __launch_bounds__(TB_BLOCK) __attribute__((amdgpu_waves_per_eu(TB_WAV
     const Inst I = tab[hb];
     int32_t n = arg;
     if (bmap && !tb_pass_roles(I, arg, D, n, prev, cur, outa, outb)) return;
-    const uint32_t C = I.C, Lx = I.P, Ly = I.Lm;
-    const uint32_t h = (uint32_t)I.tbh, Wn = TB_BLOCK / C, Tn = Wn - 2 * h;   // h >= D
-    const uint32_t tid = threadIdx.x, s = tid / C, c = tid - s * C;
+    const uint32_t C = I.C, Gs = I.tbg, Cg = C / Gs, Lx = I.P, Ly = I.Lm;
+    const uint32_t h = (uint32_t)I.tbh, Wn = TB_BLOCK / Cg, Tn = Wn - 2 * h;   // h >= D
+    const uint32_t tid = threadIdx.x, s = tid / Cg, cl = tid - s * Cg;
     const bool hd = I.has_diag;
     const S hop = SPIN ? (S)0 : G::lds(I.hop, 0);
     const bool first = (n == 0);
     const T zero = (T)(S)0;
     const T two = (T)(S)2;
-    const ItemRange ir = item_range(I, I.nct, I.nseg);
+    const ItemRange ir = item_range(I, I.nct * Gs, I.nseg);
     for (uint32_t it = ir.first; it < ir.count; it += ir.stride) {
         const uint32_t sl = it / ir.nu;
         const uint32_t sg = ir.sb + sl;
-        const uint32_t tx = ir.ub + (it - sl * ir.nu);
+        const uint32_t unit = ir.ub + (it - sl * ir.nu);
+        const uint32_t tx = unit / Gs, c = (unit - tx * Gs) * Cg + cl;
         const uint32_t x0 = tx * Tn;
         const uint32_t xend = min(x0 + Tn, Lx);
         const uint32_t x = (x0 + Lx - h + s) % Lx;
         const uint32_t xm = (x == 0) ? Lx - 1 : x - 1;   // -x neighbour (its forward x-bond)
         const bool own = s >= h && s < Wn - h && x0 + s - h < xend;
         const uint32_t y0 = sg * I.S, y1 = min(y0 + I.S, Ly), ns = y1 - y0;
-        const uint32_t t = sg * I.nct + tx;
-        const uint32_t tl = (s >= 1) ? tid - C : tid, tr = (s + 1 < Wn) ? tid + C : tid;   // in-row neighbours
+        const uint32_t t = sg * I.nct * Gs + unit;
+        const uint32_t tl = (s >= 1) ? tid - Cg : tid, tr = (s + 1 < Wn) ? tid + Cg : tid;   // in-row neighbours
         Dots<S> acc[D];
         auto row = [&](int32_t off) { return (y0 + Ly + (uint32_t)off) % Ly; };   // y0 + off, periodic
         // level 0 (r_n): rows y-1, y, y+1 of the current iteration; diagonal d[q] of row y + 1 - q

@@ -80,16 +80,54 @@ def test_tblock_complex_matches_oracle_and_one_step(case, tb):
         assert np.abs(got - one).max() <= 1e-12
 
 
-def test_tblock_off_when_sites_are_too_wide():
-    """128 chunks per site leave a 4-site window: too narrow for any halo, so one step per pass."""
+def test_wide_sites_blocked_through_chunk_groups():
+    """128 chunks per site leave a 4-site window for the whole site: too narrow for any halo, so
+    without chunk groups the solve takes one step per pass; split into groups of 16 chunks (a
+    32-site window within L_x = 40) it is blocked, and its moments equal the one-step path's."""
     op = _spin_lat(40, 12, 0.0, 5)
-    with kpm.launch_settings(small=0, tblock=4):
-        h = kpm.Hamiltonian(op, 4.5, 0.0, kpm.F32)
-        s = kpm.Solve(h, 20, 256, wl.VEC_PHASE, 1, 0)
-        mode = kpm.lib().kpm_solve_mode(s._s)
-        s.close()
-        h.free()
-    assert mode != 3
+    modes = {}
+    for grp in (0, 8):
+        with kpm.launch_settings(small=0, tblock=4, tb_group=grp):
+            h = kpm.Hamiltonian(op, 4.5, 0.0, kpm.F32)
+            s = kpm.Solve(h, 20, 256, wl.VEC_PHASE, 1, 0)
+            modes[grp] = kpm.lib().kpm_solve_mode(s._s)
+            s.close()
+            h.free()
+    assert modes[0] != 3 and modes[8] == 3
+    lo, hi = gu.oracle_bounds(op)
+    a, b = oracle.scale_from_bounds(lo, hi, 0.01)
+    with kpm.launch_settings(small=0, tblock=4, tb_group=8):
+        got = gu.gpu_moments(op, a, b, kpm.F32, 20, 256, wl.VEC_PHASE, seed=4)
+    with kpm.launch_settings(small=0, tblock=0):
+        one = gu.gpu_moments(op, a, b, kpm.F32, 20, 256, wl.VEC_PHASE, seed=4)
+    assert np.abs(got - one).max() <= 1e-12
+
+
+@pytest.mark.parametrize("grp", [0, 4, 8, 16])
+def test_chunk_groups_match_oracle(grp):
+    """The 2D blocked kernel with the site's chunks split into groups (window of 512 / Cg sites):
+    FP64 vectors bitwise those of one-step passes, both precisions against the oracle."""
+    op = _spin_lat(300, 24, 1.0, 19)   # R = 64 phase vectors: C = 32 (FP32), 64 (FP64) chunks
+    lo, hi = gu.oracle_bounds(op)
+    a, b = oracle.scale_from_bounds(lo, hi, 0.01)
+    M, R = 45, 64
+    ref = gu.oracle_moments(op, a, b, M, R, wl.VEC_PHASE, 12)
+    for prec in (kpm.F64, kpm.F32):
+        with kpm.launch_settings(small=0, tblock=-1, tb_group=grp):
+            h = kpm.Hamiltonian(op, a, b, prec)
+            s = kpm.Solve(h, M, R, wl.VEC_PHASE, 12, 0)
+            assert kpm.lib().kpm_solve_mode(s._s) == 3
+            s.close()
+            h.free()
+            got = gu.gpu_moments(op, a, b, prec, M, R, wl.VEC_PHASE, seed=12)
+        with kpm.launch_settings(small=0, tblock=0):
+            one = gu.gpu_moments(op, a, b, prec, M, R, wl.VEC_PHASE, seed=12)
+        if prec == kpm.F64:
+            gu.assert_fp64(got, ref, f"chunk groups >= {grp}")
+            assert np.abs(got - one).max() <= 1e-15
+        else:
+            gu.assert_fp32(got, ref, f"chunk groups >= {grp}")
+            assert np.abs(got - one).max() <= 1e-12
 
 
 @pytest.mark.parametrize("tb", DEPTHS)

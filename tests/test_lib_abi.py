@@ -105,10 +105,10 @@ def test_lanczos_argument_validation(L):
 def test_launch_settings_roundtrip(L):
     old = kpm.get_launch()
     with kpm.launch_settings(elems_per_thread=2, max_blocks=1024, march=0, march_items=64, xcd_split=3, alternate=0,
-                             small=0, streaming=0, wave_mib=0, tblock=0, tb3=1):
+                             small=0, streaming=0, wave_mib=0, tblock=0, tb3=1, tb_group=0):
         assert kpm.get_launch() == {"elems_per_thread": 2, "max_blocks": 1024, "march": 0, "march_items": 64,
                                     "xcd_split": 3, "alternate": 0, "small": 0, "streaming": 0, "wave_mib": 0,
-                                    "tblock": 0, "tb3": 1}
+                                    "tblock": 0, "tb3": 1, "tb_group": 0}
     assert kpm.get_launch() == old
 
 
