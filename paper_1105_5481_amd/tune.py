@@ -2,7 +2,7 @@
 
 The recursion kernels take their work decomposition from the library's launch keys (march
 segments, XCD split, segment direction, store kind, block cap, chunks per thread, batch waves,
-steps per pass).
+steps per pass, chunk groups of 2D blocked passes, two-step passes on 3D lattices).
 The best values depend on the operator class, the lattice shape, R and the precision, so this
 module times candidates on the caller's own operators and keeps the fastest.
 
@@ -40,8 +40,10 @@ CANDIDATES: Dict[str, List[int]] = {
     "elems_per_thread": [1, 2, 4],
     "wave_mib": [0, 128, 192, 224, 256],
     "tblock": [-1, 0, 1, 3, 4, 5],
+    "tb_group": [0, 4, 8, 16],
+    "tb3": [-1, 0, 1],
 }
-LATTICE_KEYS = ["march_items", "xcd_split", "alternate", "streaming", "max_blocks", "tblock"]
+LATTICE_KEYS = ["march_items", "xcd_split", "alternate", "streaming", "max_blocks", "tblock", "tb_group", "tb3"]
 FLAT_KEYS = ["elems_per_thread", "max_blocks"]
 
 
