@@ -76,8 +76,13 @@ def tb_depth(tblock, prec, C=16, spin=False, Lx=1 << 30, group=8):
 
 def kpm_default_tblock():
     """The library's default KPM_LAUNCH_TBLOCK."""
+    return kpm_default_launch("tblock")
+
+
+def kpm_default_launch(key):
+    """The library's current value of a launch key."""
     import paper_1105_5481_amd as kpm
-    return kpm.get_launch()["tblock"]
+    return kpm.get_launch()[key]
 FP64_MFMA_PEAK_TFLOPS = 78.6
 
 
@@ -728,7 +733,7 @@ def main():
     if args.record_traffic:
         import paper_1105_5481_amd.workloads as wl
         cfg = getattr(wl, args.workload)()
-        kern = {"config2": TB3_KERNEL if kpm_default_tblock() != 0 else "k_step_march<float, OP_SPIN3>",
+        kern = {"config2": TB3_KERNEL if kpm_default_launch("tb3") == 1 else "k_step_march<float, OP_SPIN3>",
                 "config3": CONFIG3_KERNEL,
                 "config4": TB_KERNEL[tb_depth(kpm_default_tblock(), 1)]}[args.workload]
         extra = {"config2": "--no-fp64 --no-cpu-baseline --no-serve ", "config4": "--no-fp64 --no-cpu-baseline --no-serve --no-secondary ",
