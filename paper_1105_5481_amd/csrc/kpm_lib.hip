@@ -629,11 +629,14 @@ bool make_plan(const kpm_ham *h, int32_t M, int32_t R, int32_t vec, Plan &p, boo
         p.P = (uint32_t)h->L[0];
         p.Lm = (uint32_t)h->L[1];
         p.nct = (p.P + Tn - 1) / Tn;
-        // more and shorter segments than the one-step kernels (8x the item target;
+        // more and shorter segments than the one-step kernels (6x the item target;
         // measured on the 2048^2 lattice with two-step passes: 4096 items 455 us per
-        // step, 512 items 554 us)
+        // step, 512 items 554 us; with four-step passes (R = 64) 1024 / 1536 / 2048 /
+        // 2560 / 3072 / 4096 items: 524.7 / 491.9 / 471.5 / 469.5 / 466.8 / 476.4 ms
+        // per solve, FP64 three-step passes 1428.7 / 1349.4 / 1303.5 / 1277.6 / 1281.7
+        // / 1302.4 ms)
         const uint64_t units = (uint64_t)p.nct * p.tbg;
-        const uint64_t target = 8ull * (uint64_t)g_march_items;
+        const uint64_t target = 6ull * (uint64_t)g_march_items;
         uint32_t nseg = (uint32_t)((target + units - 1) / units);
         nseg = std::max<uint32_t>(1, std::min<uint32_t>(nseg, std::max<uint32_t>(1, p.Lm / 8)));
         p.S = (p.Lm + nseg - 1) / nseg;
