@@ -85,7 +85,7 @@ def lib():
         "kpm_set_launch": (i32, [i32, i32]),
         "kpm_get_launch": (i32, [i32, P]),
         "kpm_selftest_fastdiv": (i32, [ctypes.c_uint32, P, i32]),
-        "kpm_selftest_placement": (ctypes.c_int64, [P, P, P, i32, P, P, P, ctypes.c_int64]),
+        "kpm_selftest_placement": (ctypes.c_int64, [P, P, P, i32, i32, P, P, P, ctypes.c_int64]),
         "kpm_solve_remaining": (i32, [P, P]),
         "kpm_request_bytes": (sz, [pdesc, i32, i32, i32, i32]),
         "kpm_ham_bytes": (sz, [P]),

@@ -120,13 +120,16 @@ def test_no_cpu_fallback_when_library_missing(monkeypatch):
         kpm.lib()
 
 
+@pytest.mark.parametrize("wave", [0, 1])
 @pytest.mark.parametrize("split", [False, True])
 @pytest.mark.parametrize("case", range(6))
-def test_block_placement(L, case, split):
+def test_block_placement(L, case, split, wave):
     """Multi-instance launches: every block of the grid maps to one block of one instance or is idle;
-    instances split per XCD start on a multiple of 8; with at least 8 unsplit instances each of them
-    has all its blocks on one XCD (block b runs on XCD b mod 8) and the XCD loads are balanced (an
-    instance that would overload an XCD is split when it has >= 48 units)."""
+    instances split per XCD start on a multiple of 8; with at least 8 candidates for whole placement
+    (instances without a split of their own; in a static batch wave, every march instance) each of
+    them has all its blocks on one XCD (block b runs on XCD b mod 8) and the XCD loads are balanced
+    (a candidate that would overload an XCD by more than 10%, 25% in a wave, is split when it has
+    >= 48 units)."""
     g = np.random.default_rng(case)
     n = [1, 3, 8, 9, 17, 256][case]
     nb = (g.integers(1, 40, n) * 8).astype(np.uint32)
@@ -140,7 +143,7 @@ def test_block_placement(L, case, split):
     cap = int(nb.sum()) * 2 + 8 * int(nb.max())
     m = np.zeros(cap, np.uint32)
     P = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)
-    blocks = L.kpm_selftest_placement(P(nb), P(xcd), P(units), n, P(b0), P(bs), P(m), cap)
+    blocks = L.kpm_selftest_placement(P(nb), P(xcd), P(units), n, wave, P(b0), P(bs), P(m), cap)
     assert blocks > 0
     m = m[:blocks]
     seen = [set() for _ in range(n)]
@@ -153,24 +156,28 @@ def test_block_placement(L, case, split):
         j = off // bs[i]
         assert j < nb[i] and j not in seen[i]
         seen[i].add(j)
-    packed = int((xcd_in == 0).sum()) >= 8
-    assert np.all(xcd[xcd_in == 1] == 1)
+    cand = np.ones(n, bool) if (wave and n >= 8) else (xcd_in == 0)
+    packed = int(cand.sum()) >= 8
+    if not packed:
+        cand[:] = False
+    assert np.array_equal(xcd[~cand], xcd_in[~cand])     # the others keep their own split
     if not split:
-        assert np.array_equal(xcd, xcd_in)
+        assert np.all(xcd[cand] == 0)
     load = np.zeros(8)
     for i in range(n):
         assert len(seen[i]) == nb[i]
         if xcd[i] or not packed:
             assert bs[i] == 1 and b0[i] % 8 == 0
-            if xcd[i] and not xcd_in[i]:
+            if cand[i]:
                 load += nb[i] / 8.0
         else:
             assert bs[i] == 8
             load[int(b0[i]) % 8] += nb[i]
     if packed:
-        whole = nb[(xcd_in == 0)]
-        if split:    # within 10% of an even share, plus one share of a split instance
-            assert load.max() <= 1.10 * whole.sum() / 8.0 + 1e-9 + whole.max() / 8.0
+        whole = nb[cand]
+        slack = 1.25 if wave else 1.10
+        if split:    # within the slack of an even share, plus one share of a split instance
+            assert load.max() <= slack * whole.sum() / 8.0 + 1e-9 + whole.max() / 8.0
         else:        # greedy balance: XCD loads differ by at most one instance
             assert load.max() - load.min() <= whole.max()
     idle = int((m == 0xFFFFFFFF).sum())
