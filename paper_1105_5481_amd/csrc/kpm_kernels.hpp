@@ -344,6 +344,34 @@ __device__ __forceinline__ void start_words(uint64_t seed, uint64_t instance, ui
 constexpr int PHASE_BITS = 30;
 __constant__ double kpm_phase_w[PHASE_BITS][2];
 
+// The phases of NC vectors at once, k[l] = the top PHASE_BITS bits of their
+// words: every lane runs through all PHASE_BITS factors (uniform, so they come
+// from scalar loads) and takes the product z * w_j only where bit j of its k is
+// set, so the factors multiply in ascending j as defined above.  z starts at 1:
+// 1 * w_j gives w_j exactly (w_j has no zero of negative sign), the first
+// factor itself, and k = 0 gives 1.
+template <int NC>
+__device__ __forceinline__ void phase_products(const uint32_t (&k)[NC], double (&zr)[NC], double (&zi)[NC])
+{
+#pragma unroll
+    for (int l = 0; l < NC; ++l) {
+        zr[l] = 1.0;
+        zi[l] = 0.0;
+    }
+#pragma unroll 2
+    for (int j = 0; j < PHASE_BITS; ++j) {
+        const double wr = kpm_phase_w[j][0], wi = kpm_phase_w[j][1];
+#pragma unroll
+        for (int l = 0; l < NC; ++l) {
+            const double tr = zr[l] * wr - zi[l] * wi;
+            const double ti = zr[l] * wi + zi[l] * wr;
+            const bool set = (k[l] >> j) & 1u;
+            zr[l] = set ? tr : zr[l];
+            zi[l] = set ? ti : zi[l];
+        }
+    }
+}
+
 // (re, im) of xi_{r,i} given its Philox word.
 __device__ __forceinline__ void start_value(int vec, uint64_t word, uint64_t instance, uint32_t N, uint32_t i,
                                             uint32_t r, double &re, double &im)
@@ -352,25 +380,11 @@ __device__ __forceinline__ void start_value(int vec, uint64_t word, uint64_t ins
         re = (word >> 63) ? -1.0 : 1.0;
         im = 0.0;
     } else if (vec == VEC_PHASE) {
-        const uint32_t k = (uint32_t)(word >> (64 - PHASE_BITS));
-        double zr = 1.0, zi = 0.0;
-        bool started = false;
-        for (int j = 0; j < PHASE_BITS; ++j) {
-            if (!((k >> j) & 1u)) continue;
-            const double wr = kpm_phase_w[j][0], wi = kpm_phase_w[j][1];
-            if (!started) {
-                zr = wr;
-                zi = wi;
-                started = true;
-            } else {
-                const double tr = zr * wr - zi * wi;
-                const double ti = zr * wi + zi * wr;
-                zr = tr;
-                zi = ti;
-            }
-        }
-        re = zr;
-        im = zi;
+        const uint32_t k[1] = {(uint32_t)(word >> (64 - PHASE_BITS))};
+        double zr[1], zi[1];
+        phase_products<1>(k, zr, zi);
+        re = zr[0];
+        im = zi[0];
     } else {
         uint64_t j = (instance + (uint64_t)r) % (uint64_t)N;
         re = (j == (uint64_t)i) ? 1.0 : 0.0;
@@ -389,7 +403,21 @@ __device__ __forceinline__ typename V16<S>::T start_chunk(const Inst &I, uint32_
     uint64_t w[4] = {0, 0, 0, 0};
     if (I.vec != VEC_UNIT) start_words(I.seed, I.instance, i, r0 / 4, w);
     T v;
-    if (I.cplx) {
+    if (I.cplx && I.vec == VEC_PHASE) {
+        // the chunk's W / 2 phases in one pass over the factors
+        constexpr int NC = W / 2;
+        uint32_t k[NC];
+        double zr[NC], zi[NC];
+#pragma unroll
+        for (int l = 0; l < NC; ++l) k[l] = (uint32_t)(w[(r0 + l) & 3] >> (64 - PHASE_BITS));
+        phase_products<NC>(k, zr, zi);
+#pragma unroll
+        for (int l = 0; l < NC; ++l) {
+            const bool in = r0 + l < (uint32_t)I.R;
+            v[2 * l] = in ? (S)zr[l] : (S)0;
+            v[2 * l + 1] = in ? (S)zi[l] : (S)0;
+        }
+    } else if (I.cplx) {
 #pragma unroll
         for (int l = 0; l < W / 2; ++l) {
             const uint32_t r = r0 + l;
