@@ -228,6 +228,34 @@ def test_batched_waves_bitwise(prec):
         h.free()
 
 
+@pytest.mark.parametrize("prec", [kpm.F64, kpm.F32])
+def test_batched_wave_placement_bitwise(prec):
+    """Ten spin cubes of one kernel class in one wave, the largest big enough for a plan of their
+    own that splits them over the XCDs: the wave balances them whole over the XCDs by load, which
+    changes only which block runs a work item, so every result equals the solo solve bit for bit
+    (and the FP64 ones the oracle)."""
+    sizes = [6, 9, 12, 16, 20, 24, 30, 36, 46, 48]
+    ops = [wl.spin_cubic_lattice(L, seed=90 + L) for L in sizes]
+    hs, ab = [], []
+    for op in ops:
+        lo, hi = gu.oracle_bounds(op)
+        a, b = oracle.scale_from_bounds(lo, hi, 0.01)
+        hs.append(kpm.Hamiltonian(op, a, b, prec))
+        ab.append((a, b))
+    M, R = 24, 16
+    seeds, insts = list(range(60, 70)), list(range(10))
+    got = [m.cpu().numpy() for m in kpm.moments_batched(hs, M, R, wl.VEC_PHASE, seeds, insts)]
+    for k, h in enumerate(hs):
+        solo = kpm.moments(h, M, R, wl.VEC_PHASE, seeds[k], insts[k]).cpu().numpy()
+        assert np.array_equal(got[k], solo), (sizes[k], k)
+    if prec == kpm.F64:
+        for k in (1, 8):
+            ref = gu.oracle_moments(ops[k], ab[k][0], ab[k][1], M, R, wl.VEC_PHASE, seeds[k], insts[k])
+            gu.assert_fp64(got[k], ref, f"wave placement L={sizes[k]}")
+    for h in hs:
+        h.free()
+
+
 def test_mixed_operator_batch():
     ops = [wl.square_lattice(20, W=1.0, seed=40), wl.spin_cubic_lattice(6, seed=41), wl.cubic_lattice(7, W=1.0, seed=42)]
     hs = []
