@@ -355,10 +355,14 @@ kpm_status kpm_start_vectors(int32_t vec, int32_t complex_layout, uint64_t seed,
 /* Launch-shape tuning (host state, process-wide; applies to solves begun
  * afterwards).  Keys:
  *   KPM_LAUNCH_ELEMS_PER_THREAD  flat kernels: 16-byte chunks per thread per tile (1, 2 or 4)
- *   KPM_LAUNCH_MAX_BLOCKS        blocks per instance per launch (multiple of 8, >= 8)
+ *   KPM_LAUNCH_MAX_BLOCKS        blocks per instance per launch (multiple of 8, >= 8; default
+ *                                2048)
  *   KPM_LAUNCH_MARCH             1: lattices use the march kernels; 0: the flat kernels
  *   KPM_LAUNCH_MARCH_ITEMS       target work items per instance when the march axis is cut
- *                                into segments (fewer items -> longer segments; default 512)
+ *                                into segments (fewer items -> longer segments; default 512).
+ *                                FP32 3D spin solves whose vectors stream from HBM
+ *                                (KPM_LAUNCH_STREAMING) take 4x this target on a quarter of
+ *                                KPM_LAUNCH_MAX_BLOCKS blocks
  *   KPM_LAUNCH_XCD_SPLIT         how an instance's work items are split over the 8 XCDs:
  *                                0 automatic, 1 by column tiles, 2 by march segments, 3 none
  *   KPM_LAUNCH_ALTERNATE         1: odd march segments walk downwards

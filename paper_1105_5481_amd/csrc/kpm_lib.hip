@@ -509,6 +509,7 @@ struct Plan {
     uint32_t tbg;     // 2D temporal blocking: chunk groups per site
     int32_t tbh;      // temporal blocking: x-tile halo = steps of the deepest pass (1 .. 6)
     uint64_t state;   // bytes the recursion touches per step (vectors + operator)
+    uint32_t grid_cap;   // most blocks per launch (0: KPM_LAUNCH_MAX_BLOCKS)
 };
 
 // Halo (= steps of the deepest pass, 2 for pairs) of a temporally blocked solve.
@@ -656,7 +657,13 @@ bool make_plan(const kpm_ham *h, int32_t M, int32_t R, int32_t vec, Plan &p, boo
         p.Lm = (uint32_t)(h->dim == 3 ? h->L[2] : h->L[1]);
         const uint64_t PC = (uint64_t)p.P * p.C;
         p.nct = (uint32_t)((PC + BLOCK - 1) / BLOCK);
-        uint32_t nseg = (uint32_t)((g_march_items + p.nct - 1) / p.nct);
+        // FP32 3D spin hopping whose vectors stream from HBM: 4x the item target
+        // (shorter segments) on a quarter of the blocks
+        const bool spin_stream = h->opk == OP_SPIN3 && h->prec == KPM_F32 &&
+                                 stream_choice(2ull * h->N * p.Rs * p.esz + (uint64_t)h->N * 7 * p.esz) == 1;
+        p.grid_cap = spin_stream ? std::max<uint32_t>(8, (uint32_t)g_max_blocks / 32 * 8) : (uint32_t)g_max_blocks;
+        const uint64_t items = spin_stream ? 4ull * (uint64_t)g_march_items : (uint64_t)g_march_items;
+        uint32_t nseg = (uint32_t)((items + p.nct - 1) / p.nct);
         nseg = std::max<uint32_t>(1, std::min<uint32_t>(nseg, std::max<uint32_t>(1, p.Lm / 8)));
         p.S = (p.Lm + nseg - 1) / nseg;
         p.nseg = (p.Lm + p.S - 1) / p.S;
@@ -675,7 +682,7 @@ bool make_plan(const kpm_ham *h, int32_t M, int32_t R, int32_t vec, Plan &p, boo
         p.xcd = p.tiles >= XCD_MIN_ITEMS ? 1 : 0;
     }
     const uint32_t nb = (p.tiles + 7) / 8 * 8;
-    p.nb = std::min<uint32_t>(nb, (uint32_t)g_max_blocks);
+    p.nb = std::min<uint32_t>(nb, p.grid_cap ? p.grid_cap : (uint32_t)g_max_blocks);
     p.K = M / 2;
     p.P_slots = std::min(p.K + 1, PSLOTS_MAX);
     p.part_bytes = align256((size_t)p.P_slots * p.tiles * 4 * sizeof(double));
