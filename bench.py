@@ -10,7 +10,8 @@ M = 4096 moments, R = 64 +-1 vectors as one block, FP32 recursion with FP64 mome
 accumulation; the plain FP64 path is timed beside it.  The cache-resident 3D 64^3 spin
 lattice (complex64, M = 1024, R = 32) and a short serving stream are reported on the same line.
 
-Prints one JSON line.  `--gpus N` with N > 1 is refused: this build measures one GPU.
+Prints one JSON line.  `--gpus N` with N > 1 is refused: the path runs on one GPU (no multi-GPU
+execution is implemented).
 """
 from __future__ import annotations
 
@@ -748,7 +749,7 @@ def main():
         return
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "multi-GPU execution is not implemented; --gpus must be 1"}))
         log("bench.py: only --gpus 1 is supported (one process on one GPU)")
         sys.exit(2)
 
