@@ -428,7 +428,11 @@ def serving_leg(n_requests, logN_max, load, seed=1005, fp64_stable=0.0, capacity
         srv.close()
         svc64 = np.array([r.t_done - r.t_admit for r in plain if r.status == "ok"])
         cap64 = len(svc64) / svc64.sum()
-        log(f"bench: load {ld}: FP64 FCFS {latency_stats(plain)}")
+        # accuracy of the served FP32 moments against the plain FP64 path on the same requests
+        by_id = {r.rid: r for r in plain if r.status == "ok"}
+        dmu = max(float(np.abs(r.mu - by_id[r.rid].mu).max()) for r in served
+                  if r.status == "ok" and r.rid in by_id)
+        log(f"bench: load {ld}: FP64 FCFS {latency_stats(plain)}; FP32 vs FP64 max |dmu| {dmu:.2e}")
         out["loads"].append({
             "offered_load": ld, "arrival_rate_req_per_s": ld * capacity,
             "fp32_served": latency_stats(served), "max_concurrent_solves": conc,
@@ -436,7 +440,8 @@ def serving_leg(n_requests, logN_max, load, seed=1005, fp64_stable=0.0, capacity
             "fp64_isolated_service_ms": {"p50": float(np.percentile(svc64, 50) * 1e3),
                                          "p99": float(np.percentile(svc64, 99) * 1e3),
                                          "mean": float(svc64.mean() * 1e3)},
-            "fp64_capacity_req_per_s": cap64, "fp64_stable_at_this_rate": bool(ld * capacity < cap64)})
+            "fp64_capacity_req_per_s": cap64, "fp64_stable_at_this_rate": bool(ld * capacity < cap64),
+            "speedup_fp32_capacity_over_fp64": capacity / cap64, "fp32_vs_fp64_max_abs_dmu": dmu})
     if fp64_stable > 0 and out["loads"]:
         rate = fp64_stable * out["loads"][-1]["fp64_capacity_req_per_s"]
         arrivals = np.cumsum(gaps / rate)
