@@ -256,6 +256,33 @@ def test_batched_wave_placement_bitwise(prec):
         h.free()
 
 
+def test_batched_wave_mixed_kinds_bitwise():
+    """A wave with single-workgroup, CSR, 2D march and at least eight 3D spin march instances (each
+    kernel class placed on its own, the spin cubes whole per XCD): every result equals its solo
+    solve bit for bit, also when the wave budget cuts the batch into several waves."""
+    ops = ([wl.spin_cubic_lattice(L, seed=400 + L) for L in (5, 13, 15, 17, 19, 21, 23, 26, 29, 31)] +
+           [wl.lattice_to_csr(wl.square_lattice(25, W=1.0, seed=420)), wl.square_lattice(90, W=2.0, seed=421)])
+    hs = []
+    for op in ops:
+        lo, hi = gu.oracle_bounds(op)
+        a, b = oracle.scale_from_bounds(lo, hi, 0.01)
+        hs.append(kpm.Hamiltonian(op, a, b, kpm.F32))
+    n = len(hs)
+    Ms = [20 + 3 * k for k in range(n)]
+    Rs = [8 + (k % 5) for k in range(n)]      # >= 4 chunks per site: every cube from L = 13 up marches
+    seeds, insts = [70 + k for k in range(n)], list(range(n))
+    with kpm.launch_settings(tblock=0):
+        solo = [kpm.moments(h, Ms[k], Rs[k], wl.VEC_PHASE, seeds[k], insts[k]).cpu().numpy()
+                for k, h in enumerate(hs)]
+    for wave in (0, 2):
+        with kpm.launch_settings(wave_mib=wave):
+            got = [m.cpu().numpy() for m in kpm.moments_batched(hs, Ms, Rs, wl.VEC_PHASE, seeds, insts)]
+        for k in range(n):
+            assert np.array_equal(got[k], solo[k]), (wave, k)
+    for h in hs:
+        h.free()
+
+
 def test_mixed_operator_batch():
     ops = [wl.square_lattice(20, W=1.0, seed=40), wl.spin_cubic_lattice(6, seed=41), wl.cubic_lattice(7, W=1.0, seed=42)]
     hs = []
