@@ -65,14 +65,15 @@ def tb_groups(C, Lx, group=8):
 
 def tb_depth(tblock, prec, C=16, spin=False, Lx=1 << 30, group=8):
     """Steps of the deepest pass of a temporally blocked solve for a KPM_LAUNCH_TBLOCK value (the
-    library's rule: -1 gives 4 for FP32 real hopping and 3 otherwise; 1 pairs; at most a quarter of
-    the window of 512 / Cg sites, Cg = 16-byte chunks per site in one chunk group)."""
+    library's rule: -1 gives 4 for FP32 real hopping and for FP32 spin hopping in chunk groups, 3
+    otherwise; 1 pairs; at most a quarter of the window of 512 / Cg sites, Cg = 16-byte chunks per
+    site in one chunk group)."""
+    G = tb_groups(C, Lx, group)
     if tblock < 0:
-        d = 3 if (prec == 0 or spin) else 4
+        d = 3 if (prec == 0 or (spin and G == 1)) else 4
     else:
         d = tblock if tblock >= 3 else 2
-    Cg = C // tb_groups(C, Lx, group)
-    return min(d, 512 // Cg // 4)
+    return min(d, 512 // (C // G) // 4)
 
 
 def kpm_default_tblock():

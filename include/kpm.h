@@ -387,7 +387,8 @@ kpm_status kpm_start_vectors(int32_t vec, int32_t complex_layout, uint64_t seed,
  *                                D = 3 .. 6: D steps per pass where at least D remain (only
  *                                r_{n+D-1} and r_{n+D} are written; x-tiles with D-site
  *                                halos, L_y >= 2D), shorter passes for the rest; -1
- *                                (default): D = 4 for FP32 real hopping, else 3; 1: two
+ *                                (default): D = 4 for FP32 real hopping and for FP32
+ *                                spin hopping split into chunk groups, else 3; 1: two
  *                                steps per pass (L_y >= 4); 0: one step per pass.  D is
  *                                capped at 128/C (a quarter of the 512/C-site window);
  *                                below 2 the solve takes one step per pass.  Batched

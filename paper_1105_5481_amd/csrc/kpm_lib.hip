@@ -514,19 +514,21 @@ struct Plan {
 
 // Halo (= steps of the deepest pass, 2 for pairs) of a temporally blocked solve.
 // Default (-1), measured on 2048^2 lattices: FP32 real hopping four steps (R = 64: 2.5x
-// one step per pass); FP32 spin hopping three (R = 16 / 32 / 64: 1.53x / 1.68x / 1.44x,
-// 1-10% faster than four); FP64 three (four need over 150 VGPRs and run slower; spin
-// R = 8: 1.27x).
-int tb_depth(int prec, int opk)
+// one step per pass); FP32 spin hopping three (R = 16 / 32: 1.53x / 1.68x, 1-10% faster
+// than four) unless its sites are split into chunk groups (grouped), where four are
+// 2.4-5.6% faster (us per step, three -> four: 2048^2 R = 64 684.1 -> 653.9, 1024^2
+// R = 48 163.4 -> 159.1, R = 64 195.7 -> 191.0, 512^2 R = 64 71.0 -> 67.0); FP64 three
+// (four need over 150 VGPRs and run slower; spin R = 8: 1.27x).
+int tb_depth(int prec, int opk, bool grouped = false)
 {
-    if (g_tblock < 0) return (prec == KPM_F64 || opk == OP_SPIN2) ? 3 : 4;
+    if (g_tblock < 0) return (prec == KPM_F64 || (opk == OP_SPIN2 && !grouped)) ? 3 : 4;
     return g_tblock >= 3 ? g_tblock : 2;
 }
-// The halo actually used with C chunks per site: at most a quarter of the window of
-// TB_BLOCK / C sites, so that at least half of it is owned.
-int tb_halo(int prec, int opk, uint32_t C)
+// The halo actually used with C chunks per site (in groups or not): at most a quarter
+// of the window of TB_BLOCK / C sites, so that at least half of it is owned.
+int tb_halo(int prec, int opk, uint32_t C, bool grouped = false)
 {
-    return std::min<int>(tb_depth(prec, opk), (int)(TB_BLOCK / C / 4));
+    return std::min<int>(tb_depth(prec, opk, grouped), (int)(TB_BLOCK / C / 4));
 }
 
 // Chunk groups of a 2D blocked solve whose window would be narrower than 32
@@ -615,9 +617,11 @@ bool make_plan(const kpm_ham *h, int32_t M, int32_t R, int32_t vec, Plan &p, boo
         p.tiles = SMALL_WAVES;   // per-wave dot partials
         p.xcd = 0;
     } else if (allow_tb && g_tblock && g_march && (h->opk == OP_REAL2 || h->opk == OP_SPIN2) &&
-               tb_halo(h->prec, h->opk, p.C / tb_groups(p.C, (uint32_t)h->L[0])) >= 2 &&
+               tb_halo(h->prec, h->opk, p.C / tb_groups(p.C, (uint32_t)h->L[0]),
+                       tb_groups(p.C, (uint32_t)h->L[0]) > 1) >= 2 &&
                h->L[0] >= TB_BLOCK / (p.C / tb_groups(p.C, (uint32_t)h->L[0])) &&
-               h->L[1] >= 2 * tb_halo(h->prec, h->opk, p.C / tb_groups(p.C, (uint32_t)h->L[0]))) {
+               h->L[1] >= 2 * tb_halo(h->prec, h->opk, p.C / tb_groups(p.C, (uint32_t)h->L[0]),
+                                      tb_groups(p.C, (uint32_t)h->L[0]) > 1)) {
         // several steps per pass: the site's chunks in tbg groups, windows of
         // floor(TB_BLOCK/Cg) sites of one group (Cg = C/tbg; threads beyond window * Cg
         // idle), x-tiles of the window less 2 tbh halo sites, segments of rows
@@ -625,7 +629,7 @@ bool make_plan(const kpm_ham *h, int32_t M, int32_t R, int32_t vec, Plan &p, boo
         p.nbuf = 4;
         p.tbg = tb_groups(p.C, (uint32_t)h->L[0]);
         const uint32_t Cg = p.C / p.tbg;
-        p.tbh = tb_halo(h->prec, h->opk, Cg);
+        p.tbh = tb_halo(h->prec, h->opk, Cg, p.tbg > 1);
         const uint32_t Tn = TB_BLOCK / Cg - 2 * (uint32_t)p.tbh;
         p.P = (uint32_t)h->L[0];
         p.Lm = (uint32_t)h->L[1];

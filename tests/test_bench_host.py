@@ -33,6 +33,8 @@ def test_chunk_group_and_depth_rules():
     assert bench.tb_depth(-1, 1, 16) == 4          # FP32 real hopping
     assert bench.tb_depth(-1, 0, 16) == 3          # FP64
     assert bench.tb_depth(-1, 1, 16, spin=True) == 3
+    assert bench.tb_depth(-1, 1, 32, spin=True, Lx=2048) == 4   # spin hopping in chunk groups
+    assert bench.tb_depth(-1, 0, 32, spin=True, Lx=2048) == 3
     assert bench.tb_depth(6, 1, 64, Lx=8) == 2     # capped at a quarter of a 8-site window
 
 
